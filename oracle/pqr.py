@@ -1,0 +1,346 @@
+"""Plain FP64 implementation of weighted-l1 PQR and of FS-QRPPA (Algorithm 1).
+
+Test infrastructure only (see the package docstring).  Everything here is
+written for a reader to check against the paper by eye: no blocking, fusion
+or reordering beyond what the equations state.
+
+Conventions
+-----------
+* ``X1`` is the n x (p+1) design WITH the intercept as column 0 (Sec. 1, the
+  feature vector x_i = (1, x_i1, ..., x_ip)).
+* ``lam`` is the (p+1)-vector of penalty weights with lam[0] = 0, so the
+  intercept is never penalised (weighted-l1 penalty equation).
+* A partition of the columns into G contiguous blocks (decomposition of X
+  into X_1..X_G) is a list ``blocks`` of index arrays over 0..p.
+
+Pins (see tests/test_oracle_*.py): prox maps against brute-force 1-D
+minimisation; lambda_max and the intercept-only fit against the sample-quantile
+closed form; the full solve against an exact rational simplex, vertex
+enumeration and HiGHS; the certificate by weak duality; the step by the
+non-increase of the H-norm successive difference.
+"""
+import math
+
+import numpy as np
+
+
+# ----------------------------------------------------------------------------
+# Objective (eq. vanilla_QR with the weighted-l1 penalty)
+# ----------------------------------------------------------------------------
+
+def pinball(u, tau):
+    """rho_tau(u) = (tau - 1{u < 0}) u, elementwise (Sec. 1)."""
+    u = np.asarray(u, dtype=np.float64)
+    return (tau - (u < 0).astype(np.float64)) * u
+
+
+def _sum(a):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    return math.fsum(a) if a.size <= 200_000 else float(np.sum(a))
+
+
+def objective(X1, y, beta, tau, lam):
+    """P(beta) = (1/n) sum_i rho_tau(y_i - x_i^T beta) + sum_{j>=1} lam_j |beta_j|."""
+    n = X1.shape[0]
+    r = y - X1 @ beta
+    return _sum(pinball(r, tau)) / n + _sum(np.abs(lam * beta))
+
+
+def penalty(beta, lam):
+    return _sum(np.abs(lam * beta))
+
+
+# ----------------------------------------------------------------------------
+# Closed-form updates (eqs. beta_update and z_update)
+# ----------------------------------------------------------------------------
+
+def beta_prox(beta_g, v_g, lam_g, eta_g):
+    """beta_update: (1/eta)[(eta b + v - lam)_+ - (-eta b - v - lam)_+], v = X_g^T theta."""
+    a = eta_g * beta_g + v_g
+    return (np.maximum(a - lam_g, 0.0) - np.maximum(-a - lam_g, 0.0)) / eta_g
+
+
+def z_prox(z, theta, tau, n, mu):
+    """z_update: (z + theta/mu - tau/(n mu))_+ - (-z - theta/mu - (1-tau)/(n mu))_+."""
+    u = z + theta / mu
+    return np.maximum(u - tau / (n * mu), 0.0) - np.maximum(-u - (1.0 - tau) / (n * mu), 0.0)
+
+
+# ----------------------------------------------------------------------------
+# Partition and step sizes (decomposition of X; M_g = eta_g I, eta_g > mu Lambda_max)
+# ----------------------------------------------------------------------------
+
+def partition(p, G, align=1):
+    """Contiguous near-equal blocks over the p feature columns; block 0 also holds
+    the intercept.  Feature boundaries b_g = align * floor(g * ceil(p/align) / G),
+    b_G = p.  Returns a list of index arrays over the full columns 0..p."""
+    units = -(-p // align)
+    if not 1 <= G <= units:
+        raise ValueError("need 1 <= G <= ceil(p / align)")
+    b = [min(p, align * ((g * units) // G)) for g in range(G)] + [p]
+    blocks = []
+    for g in range(G):
+        cols = np.arange(1 + b[g], 1 + b[g + 1])
+        if g == 0:
+            cols = np.concatenate([[0], cols])
+        blocks.append(cols)
+    return blocks
+
+
+def block_lambda_max(Xg):
+    """Largest eigenvalue of X_g^T X_g, computed as the top singular value squared."""
+    if min(Xg.shape) <= 400:
+        s = np.linalg.svd(Xg, compute_uv=False)
+        return float(s[0] ** 2)
+    from scipy.sparse.linalg import svds
+    s = svds(Xg, k=1, return_singular_vectors=False, tol=1e-12, random_state=0)
+    return float(s[0] ** 2)
+
+
+def step_sizes(X1, blocks, mu, margin=0.01):
+    """eta_g = (1 + margin) * mu * Lambda_max(X_g^T X_g) (text after eq. fsppa_update)."""
+    return np.array([(1.0 + margin) * mu * block_lambda_max(X1[:, b]) for b in blocks])
+
+
+def default_mu(y, G, scale=1.0):
+    """Reading of the unstated augmentation parameter: mu = scale*sqrt(G+1)/(n sd(y))."""
+    n = len(y)
+    return scale * math.sqrt(G + 1.0) / (n * float(np.std(y)))
+
+
+# ----------------------------------------------------------------------------
+# Algorithm 1 (FS-QRPPA), one step and the loop
+# ----------------------------------------------------------------------------
+
+def fsqrppa_step(X1, y, tau, lam, blocks, mu, eta, beta, z, theta):
+    """One pass of the while-loop body of Algorithm 1, in its order:
+    parallel-for over blocks (beta_update), then z (z_update), then theta
+    (third line of eq. fsppa_update).  Returns the new (beta, z, theta)."""
+    n = X1.shape[0]
+    G = len(blocks)
+    beta_new = beta.copy()
+    for g, cols in enumerate(blocks):
+        v_g = X1[:, cols].T @ theta
+        beta_new[cols] = beta_prox(beta[cols], v_g, lam[cols], eta[g])
+    z_new = z_prox(z, theta, tau, n, mu)
+    r_new = sum(X1[:, cols] @ beta_new[cols] for cols in blocks) + z_new - y
+    r_old = sum(X1[:, cols] @ beta[cols] for cols in blocks) + z - y
+    theta_new = theta - (mu / (G + 1.0)) * (2.0 * r_new - r_old)
+    return beta_new, z_new, theta_new
+
+
+def h_norm_sq(X1, blocks, mu, eta, d_beta, d_z, d_theta):
+    """||dw||_H^2 with H = [[D, A^T], [A, ((G+1)/mu) I]], D = diag(eta_g I, mu I),
+    A = [X, I]: the metric in which the iteration is a proximal point step
+    (Theorem 1 names such an H; its form is derived from eq. fsppa_update)."""
+    G = len(blocks)
+    q = sum(eta[g] * float(d_beta[c] @ d_beta[c]) for g, c in enumerate(blocks))
+    q += mu * float(d_z @ d_z)
+    q += 2.0 * float(d_theta @ (X1 @ d_beta + d_z))
+    q += ((G + 1.0) / mu) * float(d_theta @ d_theta)
+    return q
+
+
+def zero_start(y, p1):
+    """beta = 0, z = y, theta = 0 (so the first residual Xbeta + z - y is 0)."""
+    return np.zeros(p1), np.array(y, dtype=np.float64), np.zeros(len(y))
+
+
+def fsqrppa(X1, y, tau, lam, blocks, mu, eta, start=None, max_iter=100_000,
+            tol_gap=1e-10, check_every=10, record=False):
+    """Iterate Algorithm 1 until the FP64 relative duality gap (dual_certificate)
+    is at most tol_gap.  Returns dict(beta, z, theta, iters, rel_gap, history)."""
+    n, p1 = X1.shape
+    beta, z, theta = zero_start(y, p1) if start is None else (np.array(s, dtype=np.float64)
+                                                              for s in start)
+    hist = []
+    cert = dual_certificate(X1, y, tau, lam, beta, theta)
+    k = 0
+    while k < max_iter:
+        b1, z1, t1 = fsqrppa_step(X1, y, tau, lam, blocks, mu, eta, beta, z, theta)
+        if record:
+            hist.append(h_norm_sq(X1, blocks, mu, eta, b1 - beta, z1 - z, t1 - theta))
+        beta, z, theta = b1, z1, t1
+        k += 1
+        if k % check_every == 0:
+            cert = dual_certificate(X1, y, tau, lam, beta, theta)
+            if cert["rel_gap"] <= tol_gap:
+                break
+    cert = dual_certificate(X1, y, tau, lam, beta, theta)
+    return dict(beta=beta, z=z, theta=theta, iters=k, rel_gap=cert["rel_gap"],
+                gap=cert["gap"], primal=cert["primal"], dual=cert["dual"], history=hist)
+
+
+# ----------------------------------------------------------------------------
+# lambda_max and the null fit (project reading; the paper does not define it)
+# ----------------------------------------------------------------------------
+
+def tau_quantile(y, tau):
+    """q = y_(ceil(n tau)), the tau-quantile of the sample (inf{t : F_n(t) >= tau},
+    the definition of the conditional quantile in the notation paragraph)."""
+    ys = np.sort(np.asarray(y, dtype=np.float64))
+    n = len(ys)
+    k = max(1, math.ceil(n * tau - 1e-12))
+    return float(ys[k - 1])
+
+
+def quantile_minimizers(y, tau):
+    """Closed form of argmin_c sum rho_tau(y_i - c): [y_(n tau), y_(n tau + 1)] if
+    n tau is an integer, else {y_(ceil(n tau))}.  Returns (lo, hi)."""
+    ys = np.sort(np.asarray(y, dtype=np.float64))
+    n = len(ys)
+    nt = n * tau
+    if abs(nt - round(nt)) < 1e-12 and 1 <= round(nt) < n:
+        k = int(round(nt))
+        return float(ys[k - 1]), float(ys[k])
+    k = math.ceil(nt)
+    return float(ys[k - 1]), float(ys[k - 1])
+
+
+def null_dual(y, tau):
+    """psi with psi_i = tau (y_i > q), tau - 1 (y_i < q), and the common value on
+    ties with q that makes sum psi = 0.  Returns (q, psi)."""
+    y = np.asarray(y, dtype=np.float64)
+    q = tau_quantile(y, tau)
+    above, below, tie = y > q, y < q, y == q
+    psi = np.where(above, tau, tau - 1.0)
+    c = -(tau * above.sum() + (tau - 1.0) * below.sum()) / tie.sum()
+    psi[tie] = c
+    return q, psi
+
+
+def lambda_max(X1, y, tau, weights=None):
+    """Smallest lambda at which (q, 0, ..., 0) is optimal: max_{j>=1} |x_j^T psi| / (n w_j)
+    over columns with w_j > 0 (follows from the KKT conditions of Prop. 1)."""
+    n, p1 = X1.shape
+    _, psi = null_dual(y, tau)
+    s = np.abs(X1[:, 1:].T @ psi) / n
+    w = np.ones(p1 - 1) if weights is None else np.asarray(weights, dtype=np.float64)[1:]
+    pos = w > 0
+    return float(np.max(s[pos] / w[pos])) if pos.any() else 0.0
+
+
+# ----------------------------------------------------------------------------
+# Dual certificate and KKT check (Lagrangian eq. main_lagrangian, Prop. 1)
+# ----------------------------------------------------------------------------
+
+def project_box_sum(theta, lo, hi, iters=200):
+    """theta' = clip(theta - c, lo, hi) with c chosen by bisection so sum theta' = 0."""
+    theta = np.asarray(theta, dtype=np.float64)
+    a = float(np.min(theta)) - hi
+    b = float(np.max(theta)) - lo
+    for _ in range(iters):
+        c = 0.5 * (a + b)
+        s = _sum(np.clip(theta - c, lo, hi))
+        if s > 0:
+            a = c
+        else:
+            b = c
+        if b - a <= 0:
+            break
+    return np.clip(theta - 0.5 * (a + b), lo, hi)
+
+
+def dual_certificate(X1, y, tau, lam, beta, theta):
+    """Weak-duality certificate.  The dual of the constrained form is
+    max_theta y^T theta  s.t.  (tau-1)/n <= theta_i <= tau/n,  |x_j^T theta| <= lam_j
+    (lam_0 = 0 forces sum theta = 0).  theta is made feasible by a shift-and-clip
+    projection and a scaling alpha in (0, 1]; gap = P(beta) - y^T theta~ >= 0."""
+    n = X1.shape[0]
+    lo, hi = (tau - 1.0) / n, tau / n
+    tp = project_box_sum(theta, lo, hi)
+    v = X1[:, 1:].T @ tp
+    lj = lam[1:]
+    alpha = 1.0
+    for vj, l in zip(np.abs(v), lj):
+        if vj > l:
+            alpha = min(alpha, l / vj if vj > 0 else 1.0)
+    tf = alpha * tp
+    primal = objective(X1, y, beta, tau, lam)
+    dual = _sum(y * tf)
+    gap = primal - dual
+    return dict(primal=primal, dual=dual, gap=gap, rel_gap=gap / max(abs(primal), 1e-300),
+                theta_feasible=tf, alpha=alpha)
+
+
+def kkt_violation(X1, y, tau, lam, beta, theta, zero_tol=0.0):
+    """Largest violations of the optimality conditions (Prop. 1 with subgradients):
+    theta_i = tau/n (r_i > 0), (tau-1)/n (r_i < 0), in between (r_i = 0); sum theta = 0;
+    x_j^T theta = lam_j sign(beta_j) (beta_j != 0), |x_j^T theta| <= lam_j (beta_j = 0)."""
+    n = X1.shape[0]
+    r = y - X1 @ beta
+    lo, hi = (tau - 1.0) / n, tau / n
+    t_dual = np.where(r > zero_tol, np.abs(theta - hi),
+                      np.where(r < -zero_tol, np.abs(theta - lo),
+                               np.maximum(0.0, np.maximum(theta - hi, lo - theta))))
+    v = X1.T @ theta
+    nz = beta != 0
+    stat = np.where(nz, np.abs(v - lam * np.sign(beta)), np.maximum(0.0, np.abs(v) - lam))
+    return dict(dual_box=float(t_dual.max()), stationarity=float(stat.max()),
+                intercept=float(abs(v[0])))
+
+
+# ----------------------------------------------------------------------------
+# Standardisation (Sec. 6: standardised design, coefficients back-transformed)
+# ----------------------------------------------------------------------------
+
+def standardize(X):
+    """x~_ij = (x_ij - m_j)/s_j with the population sd (divisor n).  Zero-variance
+    columns get s_j = 0 and are returned as all-zero columns."""
+    X = np.asarray(X, dtype=np.float64)
+    n = X.shape[0]
+    m = X.sum(axis=0) / n
+    var = (X * X).sum(axis=0) / n - m * m
+    s = np.sqrt(np.maximum(var, 0.0))
+    Xt = np.zeros_like(X)
+    ok = s > 0
+    Xt[:, ok] = (X[:, ok] - m[ok]) / s[ok]
+    return Xt, m, s
+
+
+def with_intercept(X):
+    X = np.asarray(X, dtype=np.float64)
+    return np.hstack([np.ones((X.shape[0], 1)), X])
+
+
+def back_transform(beta_std, m, s):
+    """beta_j = beta~_j / s_j, beta_0 = beta~_0 - sum_j m_j beta~_j / s_j."""
+    b = np.zeros_like(beta_std)
+    ok = s > 0
+    b[1:][ok] = beta_std[1:][ok] / s[ok]
+    b[0] = beta_std[0] - float(np.dot(m[ok], b[1:][ok]))
+    return b
+
+
+# ----------------------------------------------------------------------------
+# Folded-concave derivatives for the L-step LLA (eqs. scad, mcp; Algorithm 2)
+# ----------------------------------------------------------------------------
+
+def scad_deriv(b, lam, a=3.7):
+    b = np.abs(np.asarray(b, dtype=np.float64))
+    return np.where(b <= lam, lam, np.where(b < a * lam, (a * lam - b) / (a - 1.0), 0.0))
+
+
+def mcp_deriv(b, lam, a=3.0):
+    b = np.abs(np.asarray(b, dtype=np.float64))
+    return np.where(b <= a * lam, lam - b / a, 0.0)
+
+
+def lla(X1, y, tau, lam, blocks, mu, eta, L=1, penalty_kind="scad", a=None, start=None,
+        **solve_kw):
+    """Algorithm 2: a weighted-l1 FS-QRPPA solve at unit weights, then L reweighted
+    solves with lam_j = p'_lam(|beta~_j|) (lam_0 stays 0), each warm-started from
+    the previous (beta, z, theta)."""
+    p1 = X1.shape[1]
+    lam_vec = np.full(p1, float(lam))
+    lam_vec[0] = 0.0
+    res = fsqrppa(X1, y, tau, lam_vec, blocks, mu, eta, start=start, **solve_kw)
+    for _ in range(L):
+        d = scad_deriv if penalty_kind == "scad" else mcp_deriv
+        kw = {} if a is None else {"a": a}
+        w = d(res["beta"], lam, **kw)
+        w[0] = 0.0
+        res = fsqrppa(X1, y, tau, w, blocks, mu, eta,
+                      start=(res["beta"], res["z"], res["theta"]), **solve_kw)
+        res["lam"] = w
+    return res

@@ -1,0 +1,345 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these compares the oracle with itself: each check uses a closed form,
+a brute-force search, an exact rational LP solve, an independent library
+(HiGHS), or an invariant of the iteration.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import lp, pqr
+
+
+# ----------------------------------------------------------------------------
+# prox maps (eqs. beta_update, z_update) against brute-force 1-D minimisation
+# ----------------------------------------------------------------------------
+
+def _argmin_1d(f, lo, hi):
+    """Dense grid then golden-section refinement of a convex 1-D function."""
+    xs = np.linspace(lo, hi, 20001)
+    fx = np.array([f(x) for x in xs])
+    k = int(np.argmin(fx))
+    a, b = xs[max(k - 1, 0)], xs[min(k + 1, len(xs) - 1)]
+    g = (math.sqrt(5) - 1) / 2
+    for _ in range(200):
+        c, d = b - g * (b - a), a + g * (b - a)
+        if f(c) <= f(d):
+            b = d
+        else:
+            a = c
+    return 0.5 * (a + b)
+
+
+@pytest.mark.parametrize("b0,v,lam,eta", [(0.3, 0.5, 0.2, 2.0), (-1.0, 0.1, 0.4, 1.5),
+                                          (0.0, -3.0, 1.0, 4.0), (0.2, -0.3, 0.05, 0.7),
+                                          (0.0, 0.1, 0.5, 1.0)])
+def test_beta_prox_is_argmin(b0, v, lam, eta):
+    # beta_argmin: argmin_b lam|b| - v b + (eta/2)(b - b0)^2
+    f = lambda b: lam * abs(b) - v * b + 0.5 * eta * (b - b0) ** 2
+    want = _argmin_1d(f, -10, 10)
+    got = pqr.beta_prox(np.array([b0]), np.array([v]), np.array([lam]), eta)[0]
+    # golden section resolves the argmin only to ~sqrt(eps); the value test is sharp
+    assert abs(got - want) < 1e-6
+    assert f(got) <= f(want) + 1e-15
+
+
+@pytest.mark.parametrize("z0,th,tau,n,mu", [(0.5, 0.01, 0.5, 10, 0.2), (-0.3, -0.02, 0.9, 10, 1.0),
+                                            (0.0, 0.0, 0.1, 5, 3.0), (1.0, -0.5, 0.3, 4, 0.5),
+                                            (0.01, 0.002, 0.7, 20, 0.05)])
+def test_z_prox_is_argmin(z0, th, tau, n, mu):
+    # second line of fsppa_update: argmin_z (1/n) rho_tau(z) - theta z + (mu/2)(z - z0)^2
+    f = lambda z: float(pqr.pinball(z, tau)) / n - th * z + 0.5 * mu * (z - z0) ** 2
+    want = _argmin_1d(f, -20, 20)
+    got = pqr.z_prox(np.array([z0]), np.array([th]), tau, n, mu)[0]
+    assert abs(got - want) < 1e-6
+    assert f(got) <= f(want) + 1e-15
+
+
+def test_pinball_values():
+    # rho_tau(z) = (tau - 1{z<0}) z
+    assert pqr.pinball(2.0, 0.3) == pytest.approx(0.6)
+    assert pqr.pinball(-2.0, 0.3) == pytest.approx(1.4)
+    assert pqr.pinball(0.0, 0.7) == 0.0
+
+
+# ----------------------------------------------------------------------------
+# closed forms: the sample quantile and lambda_max
+# ----------------------------------------------------------------------------
+
+def _tiny(seed, n, p):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, p))
+    y = X[:, 0] - 0.5 * X[:, min(1, p - 1)] + rng.standard_t(3, n)
+    return pqr.with_intercept(X), y
+
+
+@pytest.mark.parametrize("n,tau", [(31, 0.5), (40, 0.25), (57, 0.9), (50, 0.1)])
+def test_intercept_only_is_sample_quantile(n, tau):
+    rng = np.random.default_rng(n)
+    y = rng.standard_normal(n) * 3 + 1
+    X1 = np.ones((n, 1))
+    lam = np.zeros(1)
+    blocks = pqr.partition(0, 1) if False else [np.array([0])]
+    mu = pqr.default_mu(y, 1)
+    eta = pqr.step_sizes(X1, blocks, mu)
+    res = pqr.fsqrppa(X1, y, tau, lam, blocks, mu, eta, tol_gap=1e-12, max_iter=200000)
+    lo, hi = pqr.quantile_minimizers(y, tau)
+    assert res["rel_gap"] <= 1e-12
+    assert lo - 1e-7 <= res["beta"][0] <= hi + 1e-7
+    # the closed form's objective equals the solver's
+    obj_cf = float(np.mean(pqr.pinball(y - lo, tau)))
+    assert res["primal"] == pytest.approx(obj_cf, rel=1e-10)
+
+
+def test_quantile_minimizers_brute_force():
+    rng = np.random.default_rng(3)
+    for n, tau in [(10, 0.5), (11, 0.5), (12, 0.25), (7, 0.9)]:
+        y = rng.standard_normal(n)
+        lo, hi = pqr.quantile_minimizers(y, tau)
+        f = lambda c: float(np.sum(pqr.pinball(y - c, tau)))
+        best = min(f(c) for c in y)
+        assert f(lo) == pytest.approx(best, abs=1e-12)
+        assert f(hi) == pytest.approx(best, abs=1e-12)
+        # nothing outside [lo, hi] is optimal
+        assert f(lo - 1e-3) > best + 1e-9 and f(hi + 1e-3) > best + 1e-9
+
+
+@pytest.mark.parametrize("tau", [0.1, 0.5, 0.9])
+def test_lambda_max_null_solution(tau):
+    X1, y = _tiny(1, 45, 6)
+    lmax = pqr.lambda_max(X1, y, tau)
+    q, psi = pqr.null_dual(y, tau)
+    beta = np.zeros(X1.shape[1])
+    beta[0] = q
+    for f in (1.0, 1.5):
+        lam = np.full(X1.shape[1], f * lmax)
+        lam[0] = 0.0
+        cert = pqr.dual_certificate(X1, y, tau, lam, beta, psi / len(y))
+        assert abs(cert["gap"]) < 1e-12
+        val, _ = lp.highs(X1, y, tau, lam)
+        assert cert["primal"] == pytest.approx(val, rel=1e-8)
+    # just below lambda_max the null fit is no longer optimal
+    lam = np.full(X1.shape[1], 0.9 * lmax)
+    lam[0] = 0.0
+    val, _ = lp.highs(X1, y, tau, lam)
+    assert val < pqr.objective(X1, y, beta, tau, lam) - 1e-9
+
+
+def test_null_dual_is_balanced_and_in_box():
+    y = np.array([3.0, 1.0, 2.0, 2.0, 5.0, 2.0, 0.0])   # ties at the quantile
+    for tau in (0.3, 0.5, 0.8):
+        q, psi = pqr.null_dual(y, tau)
+        assert abs(psi.sum()) < 1e-12
+        assert np.all(psi >= tau - 1 - 1e-15) and np.all(psi <= tau + 1e-15)
+
+
+# ----------------------------------------------------------------------------
+# exact LP: simplex in rationals vs vertex enumeration vs the golden fixture
+# ----------------------------------------------------------------------------
+
+def _rational_instance(seed, n, p):
+    rng = np.random.default_rng(seed)
+    X1 = [[Fraction(1)] + [Fraction(int(v), 4) for v in rng.integers(-8, 9, p)] for _ in range(n)]
+    y = [Fraction(int(v), 3) for v in rng.integers(-12, 13, n)]
+    return X1, y
+
+
+@pytest.mark.parametrize("seed,n,p,tau,lamv", [(0, 6, 2, Fraction(1, 2), Fraction(1, 10)),
+                                               (1, 6, 2, Fraction(3, 10), Fraction(1, 5)),
+                                               (2, 5, 1, Fraction(7, 10), Fraction(0)),
+                                               (3, 6, 3, Fraction(9, 10), Fraction(1, 20))])
+def test_simplex_matches_vertex_enumeration(seed, n, p, tau, lamv):
+    X1, y = _rational_instance(seed, n, p)
+    lam = [Fraction(0)] + [lamv] * p
+    c, A, b = lp.lp_data(X1, y, tau, lam)
+    val, x = lp.simplex_exact(c, A, b)
+    best, beta = lp.vertex_enumeration(X1, y, tau, lam)
+    assert val == best
+    p1 = p + 1
+    beta_lp = [x[j] - x[p1 + j] for j in range(p1)]
+    assert lp.objective_exact(X1, y, beta_lp, tau, lam) == val
+
+
+def test_golden_tiny_lp():
+    """Exact optimum stored by tests/golden/make_golden.py (calls only oracle/)."""
+    import json, os
+    path = os.path.join(os.path.dirname(__file__), "golden", "tiny_lp.json")
+    cases = json.load(open(path))
+    for case in cases:
+        X1 = [[Fraction(v) for v in row] for row in case["X1"]]
+        y = [Fraction(v) for v in case["y"]]
+        lam = [Fraction(v) for v in case["lam"]]
+        tau = Fraction(case["tau"])
+        best, _ = lp.vertex_enumeration(X1, y, tau, lam)
+        assert best == Fraction(case["optimum"])
+        # the float FS-QRPPA oracle reaches the same optimum
+        Xf = np.array([[float(v) for v in r] for r in X1])
+        yf = np.array([float(v) for v in y])
+        lf = np.array([float(v) for v in lam])
+        blocks = [np.array([0, 1]), np.arange(2, Xf.shape[1])] if Xf.shape[1] > 2 else [np.arange(Xf.shape[1])]
+        mu = pqr.default_mu(yf, len(blocks))
+        eta = pqr.step_sizes(Xf, blocks, mu)
+        res = pqr.fsqrppa(Xf, yf, float(tau), lf, blocks, mu, eta, tol_gap=1e-11, max_iter=400000)
+        assert res["primal"] == pytest.approx(float(best), rel=1e-9, abs=1e-12)
+
+
+# ----------------------------------------------------------------------------
+# FS-QRPPA (Algorithm 1) against HiGHS; the certificate; KKT; H-norm monotonicity
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed,n,p,G,tau,lf,tol", [(0, 80, 30, 3, 0.5, 0.2, 1e-9),
+                                                   (1, 40, 60, 5, 0.3, 0.5, 1e-7),
+                                                   (2, 100, 20, 2, 0.8, 0.1, 1e-9)])
+def test_fsqrppa_reaches_lp_optimum(seed, n, p, G, tau, lf, tol):
+    X1, y = _tiny(seed, n, p)
+    lam = np.full(p + 1, lf * pqr.lambda_max(X1, y, tau))
+    lam[0] = 0.0
+    blocks = pqr.partition(p, G)
+    mu = pqr.default_mu(y, G)
+    eta = pqr.step_sizes(X1, blocks, mu)
+    res = pqr.fsqrppa(X1, y, tau, lam, blocks, mu, eta, tol_gap=tol, max_iter=300000)
+    val, beta_lp = lp.highs(X1, y, tau, lam)
+    assert res["rel_gap"] <= tol
+    assert val <= res["primal"] <= val * (1 + 2 * tol) + 1e-12
+    kkt = pqr.kkt_violation(X1, y, tau, lam, res["beta"], res["theta"], zero_tol=1e-7)
+    assert kkt["intercept"] < 1e-6 and kkt["stationarity"] < 1e-2 * lam.max()
+
+
+def test_certificate_weak_duality():
+    X1, y = _tiny(7, 50, 12)
+    tau = 0.4
+    lam = np.full(13, 0.15 * pqr.lambda_max(X1, y, tau))
+    lam[0] = 0
+    val, _ = lp.highs(X1, y, tau, lam)
+    rng = np.random.default_rng(0)
+    for _ in range(50):
+        beta = rng.standard_normal(13) * 0.3
+        theta = rng.standard_normal(50) * 0.02
+        c = pqr.dual_certificate(X1, y, tau, lam, beta, theta)
+        assert c["gap"] >= -1e-14
+        assert c["dual"] <= val + 1e-12          # a feasible dual point bounds P* from below
+        assert c["gap"] >= c["primal"] - val - 1e-12
+
+
+def test_h_norm_successive_difference_non_increasing():
+    X1, y = _tiny(4, 70, 40)
+    tau, G = 0.5, 4
+    lam = np.full(41, 0.2 * pqr.lambda_max(X1, y, tau))
+    lam[0] = 0
+    blocks = pqr.partition(40, G)
+    mu = pqr.default_mu(y, G)
+    eta = pqr.step_sizes(X1, blocks, mu)
+    res = pqr.fsqrppa(X1, y, tau, lam, blocks, mu, eta, tol_gap=0.0, max_iter=3000,
+                      check_every=10**9, record=True)
+    h = np.array(res["history"])
+    assert np.all(h >= -1e-18)
+    assert np.all(np.diff(h) <= 1e-12 * h[:-1] + 1e-30)
+    # Corollary 1: eventually linear decrease of the successive differences
+    tail = np.log(h[-1000:] + 1e-300)
+    slope = np.polyfit(np.arange(len(tail)), tail, 1)[0]
+    assert slope < 0
+
+
+def test_h_norm_detects_too_small_eta():
+    """With eta_g far below mu * Lambda_max the metric H is indefinite and the
+    successive differences stop decreasing, which is what the GPU divergence
+    detector relies on."""
+    X1, y = _tiny(5, 60, 30)
+    tau, G = 0.5, 2
+    lam = np.full(31, 0.2 * pqr.lambda_max(X1, y, tau))
+    lam[0] = 0
+    blocks = pqr.partition(30, G)
+    mu = pqr.default_mu(y, G)
+    eta = 0.05 * pqr.step_sizes(X1, blocks, mu)
+    res = pqr.fsqrppa(X1, y, tau, lam, blocks, mu, eta, tol_gap=0.0, max_iter=400,
+                      check_every=10**9, record=True)
+    h = np.array(res["history"])
+    assert np.any(np.diff(h) > 0)
+
+
+# ----------------------------------------------------------------------------
+# planted mistakes: the pins above must catch plausible bugs in the oracle
+# ----------------------------------------------------------------------------
+
+def _solve_small(step):
+    X1, y = _tiny(11, 40, 10)
+    tau, G = 0.3, 2
+    lam = np.full(11, 0.2 * pqr.lambda_max(X1, y, tau))
+    lam[0] = 0
+    blocks = pqr.partition(10, G)
+    mu = pqr.default_mu(y, G)
+    eta = pqr.step_sizes(X1, blocks, mu)
+    beta, z, theta = pqr.zero_start(y, 11)
+    for _ in range(20000):
+        beta, z, theta = step(X1, y, tau, lam, blocks, mu, eta, beta, z, theta)
+    val, _ = lp.highs(X1, y, tau, lam)
+    return pqr.objective(X1, y, beta, tau, lam), val
+
+
+def test_planted_mistakes_are_caught(monkeypatch):
+    good, val = _solve_small(pqr.fsqrppa_step)
+    assert good == pytest.approx(val, rel=1e-8)
+    # (a) tau and 1 - tau swapped in the z prox
+    orig = pqr.z_prox
+    monkeypatch.setattr(pqr, "z_prox", lambda z, th, tau, n, mu: orig(z, th, 1 - tau, n, mu))
+    bad, _ = _solve_small(pqr.fsqrppa_step)
+    assert abs(bad - val) > 1e-4 * val
+    monkeypatch.setattr(pqr, "z_prox", orig)
+    # (b) threshold lam/eta dropped to lam/(2 eta)
+    origb = pqr.beta_prox
+    monkeypatch.setattr(pqr, "beta_prox", lambda b, v, l, e: origb(b, v, 0.5 * l, e))
+    bad, _ = _solve_small(pqr.fsqrppa_step)
+    assert abs(bad - val) > 1e-4 * val
+
+
+# ----------------------------------------------------------------------------
+# folded-concave derivatives (eqs. scad, mcp) at hand-computed points
+# ----------------------------------------------------------------------------
+
+def test_scad_mcp_derivatives():
+    lam = 0.5
+    # SCAD, a = 3.7: lam on [0, lam]; (a lam - b)/(a - 1) on (lam, a lam); 0 beyond
+    assert pqr.scad_deriv(0.2, lam) == pytest.approx(0.5)
+    assert pqr.scad_deriv(-0.5, lam) == pytest.approx(0.5)
+    assert pqr.scad_deriv(1.0, lam) == pytest.approx((1.85 - 1.0) / 2.7)
+    assert pqr.scad_deriv(1.85, lam) == pytest.approx(0.0)
+    assert pqr.scad_deriv(5.0, lam) == 0.0
+    # MCP, a = 3: lam - b/a on [0, a lam]; 0 beyond
+    assert pqr.mcp_deriv(0.3, lam) == pytest.approx(0.4)
+    assert pqr.mcp_deriv(1.5, lam) == pytest.approx(0.0)
+    assert pqr.mcp_deriv(2.0, lam) == 0.0
+
+
+def test_lla_stage_is_weighted_l1_optimum():
+    X1, y = _tiny(9, 60, 8)
+    tau, G = 0.5, 2
+    lmax = pqr.lambda_max(X1, y, tau)
+    blocks = pqr.partition(8, G)
+    mu = pqr.default_mu(y, G)
+    eta = pqr.step_sizes(X1, blocks, mu)
+    res = pqr.lla(X1, y, tau, 0.3 * lmax, blocks, mu, eta, L=1, penalty_kind="mcp",
+                  tol_gap=1e-9, max_iter=300000)
+    val, _ = lp.highs(X1, y, tau, res["lam"])
+    assert res["primal"] == pytest.approx(val, rel=2e-9)
+
+
+# ----------------------------------------------------------------------------
+# standardisation and the back-transform
+# ----------------------------------------------------------------------------
+
+def test_standardize_and_back_transform():
+    rng = np.random.default_rng(2)
+    X = rng.integers(0, 3, (50, 8)).astype(float)
+    X[:, 3] = 1.0   # zero variance
+    Xt, m, s = pqr.standardize(X)
+    ok = s > 0
+    assert np.allclose(Xt[:, ok].mean(axis=0), 0, atol=1e-14)
+    assert np.allclose((Xt[:, ok] ** 2).sum(axis=0), 50)
+    assert s[3] == 0 and np.all(Xt[:, 3] == 0)
+    bs = rng.standard_normal(9)
+    bs[1 + 3] = 0
+    b = pqr.back_transform(bs, m, s)
+    assert np.allclose(pqr.with_intercept(Xt) @ bs, pqr.with_intercept(X) @ b)
