@@ -1,0 +1,177 @@
+/*
+ * pqr.h -- C ABI of libpqr: weighted-l1 penalized quantile regression (PQR)
+ * solved by FS-QRPPA, the feature-splitting proximal point algorithm
+ * (Algorithm 1 of "Scalable Ultra-High-Dimensional Quantile Regression with
+ * Genomic Applications", arXiv 2601.02826), on one AMD MI355X (gfx950).
+ *
+ * The problem (eq. vanilla_QR with the weighted-l1 penalty):
+ *
+ *     min_beta  (1/n) sum_i rho_tau(y_i - x_i^T beta) + sum_{j>=1} lambda_j |beta_j|,
+ *     rho_tau(u) = (tau - 1{u < 0}) u,   x_i = (1, x_i1, ..., x_ip),
+ *
+ * with lambda_j = lambda * w_j and an unpenalized intercept (lambda_0 = 0).
+ * When the design is standardized the solver works on x~_ij = (x_ij - m_j)/s_j
+ * (population sd) and reports coefficients on both scales.
+ *
+ * Conventions for every entry point:
+ *  - Every call returns a pqr_status; nothing aborts or throws across the ABI.
+ *    On failure pqr_last_error(ctx) holds a message.
+ *  - "device pointer" means memory from hipMalloc (or a PyTorch HIP tensor);
+ *    "host pointer" means ordinary process memory.
+ *  - All device work runs on the stream given in pqr_options.stream (NULL =
+ *    the default stream).  Calls on one context must not overlap.
+ */
+#ifndef PQR_H
+#define PQR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PQR_OK = 0,
+  PQR_ERR_INVALID_ARG = 1,   /* bad size, tau outside (0,1), negative or non-finite input */
+  PQR_ERR_OOM = 2,           /* device allocation failed */
+  PQR_ERR_DEVICE = 3,        /* a HIP call failed */
+  PQR_ERR_NOT_CONVERGED = 4, /* max_iter reached; outputs hold the last iterate */
+  PQR_ERR_DIVERGED = 5,      /* the H-norm monitor tripped twice after eta was doubled */
+  PQR_ERR_UNSUPPORTED = 6    /* combination of formats or options not provided */
+} pqr_status;
+
+/* Storage formats of the design matrix X (values, not the intercept). */
+typedef enum {
+  PQR_X_F64 = 0,     /* IEEE double                                           */
+  PQR_X_F32 = 1,     /* IEEE float                                            */
+  PQR_X_BF16 = 2,    /* bfloat16; exact for the dosages 0, 1, 2               */
+  PQR_X_FP8E4M3 = 3, /* OCP FP8 E4M3; exact for the dosages 0, 1, 2           */
+  PQR_X_I8 = 4,      /* unsigned byte codes (dosages 0..2, any 0..255 value)  */
+  PQR_X_2BIT = 5     /* 2-bit codes 0..3, four rows per byte                  */
+} pqr_xfmt;
+
+/* Iterate precision: the arithmetic of the FS-QRPPA state (beta, z, theta). */
+typedef enum { PQR_ITER_F32 = 0, PQR_ITER_F64 = 1 } pqr_iter_prec;
+
+/* Design matrix handed to pqr_create.
+ *  data   : device pointer, column-major, element (i, j) at data[j*ld + i],
+ *           i < n, j < p; src_fmt is PQR_X_F64, PQR_X_F32 or PQR_X_I8.
+ *           Caller-owned; pqr_create copies it into the context's own padded
+ *           store (format store_fmt), after which it may be freed.
+ *  store_fmt : internal storage; integer-valued sources may use any format,
+ *           floating sources PQR_X_F64 / PQR_X_F32 (converting a float source
+ *           to BF16 is allowed and is then lossy).
+ *  standardize : 1 = solve on standardized columns (zero-variance columns are
+ *           excluded: their coefficient is 0), 0 = use X as given.          */
+typedef struct {
+  int64_t n, p, ld;
+  int src_fmt;
+  const void* data;
+  int store_fmt;
+  int standardize;
+} pqr_design;
+
+/* Solver options.  Zero/negative values select the documented defaults. */
+typedef struct {
+  double mu;            /* augmentation parameter (eq. fsppa_update); default
+                           mu = mu_scale * sqrt(G+1) / (n * sd(y)), recomputed per y */
+  double mu_scale;      /* default 0.1                                         */
+  int G;                /* number of column blocks (decomposition of X); default 48,
+                           capped at ceil(p/16); block boundaries are multiples of 16 */
+  double eta_margin;    /* eta_g = (1 + margin) * mu * Lambda_g; default 0.01  */
+  int lanczos_steps;    /* steps of the Lanczos estimate of Lambda_g; default 40 */
+  int iter_prec;        /* pqr_iter_prec; default PQR_ITER_F32                 */
+  double tol_gap;       /* stop when the FP64 relative duality gap <= tol_gap; default 1e-6 */
+  int cert_every;       /* iterations between FP64 certificates; default 50     */
+  int64_t max_iter;     /* default 1e6                                         */
+  void* stream;         /* hipStream_t; NULL = default stream                  */
+} pqr_options;
+
+typedef struct pqr_ctx pqr_ctx;
+
+/* Solution and report.  Output arrays are host pointers supplied by the
+ * caller (any may be NULL to skip it):
+ *   beta      p+1 doubles, coefficients on the original scale (intercept first)
+ *   beta_std  p+1 doubles, coefficients on the solver's (standardized) scale
+ *   z, theta  n doubles each: the auxiliary and dual variables of Algorithm 1 */
+typedef struct {
+  double* beta;
+  double* beta_std;
+  double* z;
+  double* theta;
+  int64_t iters;        /* FS-QRPPA iterations run                              */
+  int64_t x_passes;     /* full reads of X (iterations + certificates + setup of this call) */
+  int64_t certs;        /* FP64 certificates evaluated                         */
+  int64_t nnz;          /* nonzero coefficients (intercept excluded)            */
+  double primal;        /* P(beta) in FP64                                      */
+  double dual;          /* dual objective of the feasible point built from theta */
+  double rel_gap;       /* (primal - dual) / primal                            */
+  double lambda_max;    /* smallest lambda with the null fit optimal (same tau, weights) */
+  double mu;            /* the mu used                                          */
+  double seconds;       /* wall time of the call                                */
+} pqr_result;
+
+typedef enum {
+  PQR_START_ZERO = 0,   /* beta = 0, z = y, theta = 0                           */
+  PQR_START_HOST = 1,   /* from warm->beta_std, warm->z, warm->theta (host)      */
+  PQR_START_DEVICE = 2  /* continue from the state the previous solve left on the device
+                           (warm starts along a lambda path; same y, tau and mu) */
+} pqr_start;
+
+/* Sets every field of *opt to its default. */
+void pqr_default_options(pqr_options* opt);
+
+/* Encodes X into the context's store, computes the column statistics (one
+ * pass, integer sums for integer formats), partitions the columns into G
+ * blocks and estimates Lambda_g = Lambda_max(X~_g^T X~_g) for every block by
+ * Lanczos (text after eq. fsppa_update: power method or Lanczos).
+ * On success *out owns its device memory until pqr_destroy. */
+pqr_status pqr_create(pqr_ctx** out, const pqr_design* X, const pqr_options* opt);
+
+/* Solves PQR for one (tau, lambda) by Algorithm 1.
+ *  y        host, n doubles (copied)
+ *  weights  host, p+1 doubles w_j >= 0 (w_0 ignored), or NULL for unit weights
+ *  start    pqr_start; for PQR_START_HOST, warm must point to arrays of the
+ *           sizes above (beta_std, z, theta)
+ *  out      results; see pqr_result.  On PQR_ERR_NOT_CONVERGED out still holds
+ *           the last iterate and its certificate. */
+pqr_status pqr_solve(pqr_ctx* ctx, const double* y, double tau, double lambda,
+                     const double* weights, int start, const pqr_result* warm,
+                     pqr_result* out);
+
+/* FP64 optimality report for a given point (Prop. 1 and the dual of the
+ * Lagrangian, eq. main_lagrangian).  beta_std: host p+1 doubles on the
+ * solver's scale; theta: host n doubles.  Pure: no state changes.
+ * rep[0] = primal P(beta), rep[1] = dual objective of the projected theta,
+ * rep[2] = relative gap, rep[3] = max_j |x~_j^T theta'| / lambda_j over
+ * penalized columns (<= 1 means dual feasible before scaling). */
+pqr_status pqr_kkt(pqr_ctx* ctx, const double* y, double tau, double lambda,
+                   const double* weights, const double* beta_std, const double* theta,
+                   double rep[4]);
+
+/* lambda_max for (y, tau, weights) and, optionally, the per-column score
+ * S_j = x~_j^T psi / n (host, p doubles) where psi is the null-fit dual
+ * (psi_i = tau above the tau-quantile of y, tau-1 below, balanced on ties). */
+pqr_status pqr_lambda_max(pqr_ctx* ctx, const double* y, double tau, const double* weights,
+                          double* lambda_max, double* score);
+
+/* Blocks and step sizes in use: bounds (host, G+1 ints, feature-column
+ * boundaries, block 0 also holds the intercept), Lambda (host, G doubles). */
+pqr_status pqr_blocks(pqr_ctx* ctx, int* G, int* bounds, double* Lambda);
+
+/* One or more iterations from a given state with every parameter explicit,
+ * for step-level checks.  beta_std (p+1), z (n), theta (n) are host doubles,
+ * read and overwritten; eta is host, G doubles.  Runs exactly `iters`
+ * iterations of Algorithm 1 with no stopping test. */
+pqr_status pqr_iterate(pqr_ctx* ctx, const double* y, double tau, double lambda,
+                       const double* weights, double mu, const double* eta, int64_t iters,
+                       double* beta_std, double* z, double* theta);
+
+void pqr_destroy(pqr_ctx* ctx);
+const char* pqr_last_error(const pqr_ctx* ctx);
+const char* pqr_status_string(pqr_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PQR_H */

@@ -1,0 +1,238 @@
+"""ctypes binding of libpqr (include/pqr.h): argument marshalling only.
+
+Every computation happens in the HIP library; if libpqr.so is missing this
+module raises instead of falling back to anything else.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpqr.so")
+
+# enums of pqr.h
+PQR_OK, PQR_ERR_INVALID_ARG, PQR_ERR_OOM, PQR_ERR_DEVICE = 0, 1, 2, 3
+PQR_ERR_NOT_CONVERGED, PQR_ERR_DIVERGED, PQR_ERR_UNSUPPORTED = 4, 5, 6
+FMT = {"f64": 0, "f32": 1, "bf16": 2, "fp8": 3, "i8": 4, "2bit": 5}
+ITER = {"f32": 0, "f64": 1}
+START = {"zero": 0, "host": 1, "device": 2}
+
+_c_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class pqr_design(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("p", ctypes.c_int64), ("ld", ctypes.c_int64),
+                ("src_fmt", ctypes.c_int), ("data", ctypes.c_void_p),
+                ("store_fmt", ctypes.c_int), ("standardize", ctypes.c_int)]
+
+
+class pqr_options(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_double), ("mu_scale", ctypes.c_double), ("G", ctypes.c_int),
+                ("eta_margin", ctypes.c_double), ("lanczos_steps", ctypes.c_int),
+                ("iter_prec", ctypes.c_int), ("tol_gap", ctypes.c_double),
+                ("cert_every", ctypes.c_int), ("max_iter", ctypes.c_int64),
+                ("stream", ctypes.c_void_p)]
+
+
+class pqr_result(ctypes.Structure):
+    _fields_ = [("beta", _c_dp), ("beta_std", _c_dp), ("z", _c_dp), ("theta", _c_dp),
+                ("iters", ctypes.c_int64), ("x_passes", ctypes.c_int64),
+                ("certs", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("primal", ctypes.c_double), ("dual", ctypes.c_double),
+                ("rel_gap", ctypes.c_double), ("lambda_max", ctypes.c_double),
+                ("mu", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+SYMBOLS = ["pqr_default_options", "pqr_create", "pqr_solve", "pqr_kkt", "pqr_lambda_max",
+           "pqr_blocks", "pqr_iterate", "pqr_destroy", "pqr_last_error", "pqr_status_string"]
+
+_lib = None
+
+
+def load():
+    """Load libpqr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libpqr.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, dbl, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    lib.pqr_default_options.argtypes = [ctypes.POINTER(pqr_options)]
+    lib.pqr_default_options.restype = None
+    lib.pqr_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(pqr_design),
+                               ctypes.POINTER(pqr_options)]
+    lib.pqr_create.restype = ci
+    lib.pqr_solve.argtypes = [vp, _c_dp, dbl, dbl, _c_dp, ci, ctypes.POINTER(pqr_result),
+                              ctypes.POINTER(pqr_result)]
+    lib.pqr_solve.restype = ci
+    lib.pqr_kkt.argtypes = [vp, _c_dp, dbl, dbl, _c_dp, _c_dp, _c_dp, _c_dp]
+    lib.pqr_kkt.restype = ci
+    lib.pqr_lambda_max.argtypes = [vp, _c_dp, dbl, _c_dp, _c_dp, _c_dp]
+    lib.pqr_lambda_max.restype = ci
+    lib.pqr_blocks.argtypes = [vp, ctypes.POINTER(ci), ctypes.POINTER(ci), _c_dp]
+    lib.pqr_blocks.restype = ci
+    lib.pqr_iterate.argtypes = [vp, _c_dp, dbl, dbl, _c_dp, dbl, _c_dp, i64, _c_dp, _c_dp, _c_dp]
+    lib.pqr_iterate.restype = ci
+    lib.pqr_destroy.argtypes = [vp]
+    lib.pqr_destroy.restype = None
+    lib.pqr_last_error.argtypes = [vp]
+    lib.pqr_last_error.restype = ctypes.c_char_p
+    lib.pqr_status_string.argtypes = [ci]
+    lib.pqr_status_string.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _dptr(a):
+    return None if a is None else a.ctypes.data_as(_c_dp)
+
+
+def _f64(a, n=None):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None and a.shape[0] != n:
+        raise ValueError(f"expected length {n}, got {a.shape[0]}")
+    return a
+
+
+class PQRError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+def _current_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:  # noqa: BLE001 - torch is optional plumbing
+        pass
+    return None
+
+
+class Result(dict):
+    """Solution and report of pqr_solve (attribute access for convenience)."""
+    __getattr__ = dict.__getitem__
+
+
+class Context:
+    """A design matrix resident on the GPU plus its solver state (pqr_ctx)."""
+
+    def __init__(self, data_ptr, n, p, ld=None, src_fmt="i8", store_fmt="i8", standardize=True,
+                 keepalive=None, **options):
+        lib = load()
+        self._lib = lib
+        self.n, self.p = int(n), int(p)
+        self._keep = keepalive
+        d = pqr_design(n=self.n, p=self.p, ld=int(ld if ld is not None else n),
+                       src_fmt=FMT[src_fmt], data=ctypes.c_void_p(int(data_ptr)),
+                       store_fmt=FMT[store_fmt], standardize=int(bool(standardize)))
+        o = pqr_options()
+        lib.pqr_default_options(ctypes.byref(o))
+        for k, v in options.items():
+            if k == "iter_prec":
+                v = ITER[v] if isinstance(v, str) else int(v)
+            if not hasattr(o, k):
+                raise TypeError(f"unknown option {k}")
+            setattr(o, k, v)
+        if o.stream is None:
+            o.stream = _current_stream()
+        self.options = o
+        h = ctypes.c_void_p()
+        st = lib.pqr_create(ctypes.byref(h), ctypes.byref(d), ctypes.byref(o))
+        self._h = h
+        if st != PQR_OK:
+            msg = lib.pqr_last_error(h).decode() if h.value else "pqr_create failed"
+            lib.pqr_destroy(h)
+            self._h = None
+            raise PQRError(st, msg)
+
+    @classmethod
+    def from_tensor(cls, Xcols, src_fmt=None, **kw):
+        """Xcols: a torch CUDA tensor of shape (p, n) holding X column by column
+        (i.e. X in column-major order), dtype uint8/int8, float32 or float64."""
+        import torch
+        if not Xcols.is_cuda or Xcols.dim() != 2 or Xcols.stride(1) != 1:
+            raise ValueError("Xcols must be a CUDA tensor of shape (p, n) with unit row stride")
+        if src_fmt is None:
+            src_fmt = {torch.float64: "f64", torch.float32: "f32", torch.uint8: "i8",
+                       torch.int8: "i8"}[Xcols.dtype]
+        p, n = Xcols.shape
+        return cls(Xcols.data_ptr(), n, p, ld=Xcols.stride(0), src_fmt=src_fmt, keepalive=Xcols,
+                   **kw)
+
+    def _check(self, st, ok=(PQR_OK,)):
+        if st not in ok:
+            raise PQRError(st, self._lib.pqr_last_error(self._h).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.pqr_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+    # ---- the C ABI, one method per entry point ----
+    def solve(self, y, tau, lam, weights=None, start="zero", warm=None, allow_not_converged=False):
+        y = _f64(y, self.n)
+        w = _f64(weights, self.p + 1)
+        beta = np.zeros(self.p + 1)
+        beta_std = np.zeros(self.p + 1)
+        z = np.zeros(self.n)
+        theta = np.zeros(self.n)
+        out = pqr_result(beta=_dptr(beta), beta_std=_dptr(beta_std), z=_dptr(z), theta=_dptr(theta))
+        wr = None
+        if warm is not None:
+            wb, wz, wt = _f64(warm["beta_std"], self.p + 1), _f64(warm["z"], self.n), _f64(warm["theta"], self.n)
+            wr = pqr_result(beta_std=_dptr(wb), z=_dptr(wz), theta=_dptr(wt))
+            start = "host"
+        st = self._lib.pqr_solve(self._h, _dptr(y), float(tau), float(lam), _dptr(w), START[start],
+                                 ctypes.byref(wr) if wr is not None else None, ctypes.byref(out))
+        ok = (PQR_OK, PQR_ERR_NOT_CONVERGED) if allow_not_converged else (PQR_OK,)
+        self._check(st, ok)
+        return Result(beta=beta, beta_std=beta_std, z=z, theta=theta, iters=out.iters,
+                      x_passes=out.x_passes, certs=out.certs, nnz=out.nnz, primal=out.primal,
+                      dual=out.dual, rel_gap=out.rel_gap, lambda_max=out.lambda_max, mu=out.mu,
+                      seconds=out.seconds, status=st)
+
+    def kkt(self, y, tau, lam, beta_std, theta, weights=None):
+        rep = np.zeros(4)
+        self._check(self._lib.pqr_kkt(self._h, _dptr(_f64(y, self.n)), float(tau), float(lam),
+                                      _dptr(_f64(weights, self.p + 1)),
+                                      _dptr(_f64(beta_std, self.p + 1)),
+                                      _dptr(_f64(theta, self.n)), _dptr(rep)))
+        return dict(primal=rep[0], dual=rep[1], rel_gap=rep[2], max_ratio=rep[3])
+
+    def lambda_max(self, y, tau, weights=None, score=False):
+        lm = np.zeros(1)
+        sc = np.zeros(self.p) if score else None
+        self._check(self._lib.pqr_lambda_max(self._h, _dptr(_f64(y, self.n)), float(tau),
+                                             _dptr(_f64(weights, self.p + 1)), _dptr(lm), _dptr(sc)))
+        return (lm[0], sc) if score else lm[0]
+
+    def blocks(self):
+        G = ctypes.c_int()
+        self._check(self._lib.pqr_blocks(self._h, ctypes.byref(G), None, None))
+        bounds = (ctypes.c_int * (G.value + 1))()
+        lam = np.zeros(G.value)
+        self._check(self._lib.pqr_blocks(self._h, ctypes.byref(G), bounds, _dptr(lam)))
+        return G.value, np.array(bounds[:], dtype=np.int64), lam
+
+    def iterate(self, y, tau, lam, mu, eta, iters, beta_std, z, theta, weights=None):
+        b = np.array(beta_std, dtype=np.float64)
+        zz = np.array(z, dtype=np.float64)
+        tt = np.array(theta, dtype=np.float64)
+        self._check(self._lib.pqr_iterate(self._h, _dptr(_f64(y, self.n)), float(tau), float(lam),
+                                          _dptr(_f64(weights, self.p + 1)), float(mu),
+                                          _dptr(_f64(eta)), int(iters), _dptr(b), _dptr(zz),
+                                          _dptr(tt)))
+        return b, zz, tt

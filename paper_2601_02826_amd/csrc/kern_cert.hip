@@ -1,0 +1,320 @@
+// FP64 optimality certificate and small deterministic reductions.
+//
+// The dual of the constrained form (eq. reformulated_QR) through its
+// Lagrangian (eq. main_lagrangian) is
+//     max_theta  y^T theta
+//     s.t. (tau-1)/n <= theta_i <= tau/n,  sum_i theta_i = 0 (lambda_0 = 0),
+//          |x~_j^T theta| <= lambda_j.
+// Any iterate theta is turned into a feasible point by a shift-and-clip
+// projection (the shift found by bisection) and a scaling alpha in [0, 1];
+// P(beta) - y^T theta~ then bounds the suboptimality of beta (Prop. 1).
+#include <cmath>
+
+#include "pqr_kernels.h"
+
+namespace pqr {
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_project(const T* __restrict__ theta, int64_t n,
+                                                  int64_t n_pad, double tau,
+                                                  const double* __restrict__ y,
+                                                  double* __restrict__ tp, double* out) {
+  __shared__ double red[3 * 16];
+  __shared__ double ab[2];
+  const double lo = (tau - 1.0) / (double)n, hi = tau / (double)n;
+  const int t = threadIdx.x;
+  double mn = INFINITY, mx = -INFINITY;
+  for (int64_t i = t; i < n; i += 1024) {
+    const double v = (double)theta[i];
+    mn = fmin(mn, v);
+    mx = fmax(mx, v);
+  }
+  // block min / max
+  mn = -wave_max(-mn);
+  mx = wave_max(mx);
+  if ((t & 63) == 0) { red[t >> 6] = mn; red[16 + (t >> 6)] = mx; }
+  __syncthreads();
+  if (t == 0) {
+    double a = red[0], b = red[16];
+    for (int w = 1; w < 16; ++w) { a = fmin(a, red[w]); b = fmax(b, red[16 + w]); }
+    ab[0] = a - hi;   // sum clip(theta - c) = n*hi > 0 here
+    ab[1] = b - lo;   // and n*lo < 0 here
+  }
+  __syncthreads();
+  double a = ab[0], b = ab[1];
+  for (int it = 0; it < 200; ++it) {
+    const double c = 0.5 * (a + b);
+    if (c <= a || c >= b) break;
+    double s[1] = {0.0};
+    for (int64_t i = t; i < n; i += 1024) s[0] += fmin(fmax((double)theta[i] - c, lo), hi);
+    block_sum<1024, 1, double>(s, red);
+    if (s[0] > 0) a = c; else b = c;
+  }
+  const double c = 0.5 * (a + b);
+  double q[2] = {0.0, 0.0};
+  for (int64_t i = t; i < n_pad; i += 1024) {
+    double v = 0.0;
+    if (i < n) {
+      v = fmin(fmax((double)theta[i] - c, lo), hi);
+      q[0] += v * y[i];
+      q[1] += v;
+    }
+    tp[i] = v;
+  }
+  block_sum<1024, 2, double>(q, red);
+  if (t == 0) { out[2] = q[0]; out[4] = c; out[5] = q[1]; }
+}
+
+template <typename T>
+hipError_t launch_project(const T* theta, int64_t n, int64_t n_pad, double tau, const double* y,
+                          double* theta_p, double* out, hipStream_t s) {
+  hipLaunchKernelGGL((k_project<T>), dim3(1), dim3(1024), 0, s, theta, n, n_pad, tau, y, theta_p,
+                     out);
+  return hipGetLastError();
+}
+template hipError_t launch_project<float>(const float*, int64_t, int64_t, double, const double*, double*, double*, hipStream_t);
+template hipError_t launch_project<double>(const double*, int64_t, int64_t, double, const double*, double*, double*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+template <int FMT, int RPL>
+__global__ __launch_bounds__(256) void k_dots64(Geom g, const double* __restrict__ tp,
+                                                const double* sum_tp, const double* __restrict__ cm,
+                                                const double* __restrict__ cinv,
+                                                const double* __restrict__ clam, double* v,
+                                                double* gmax) {
+  const int lane = threadIdx.x & 63;
+  const int64_t grp = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (grp >= g.ngroups()) return;
+  double acc[kGroup];
+#pragma unroll
+  for (int c = 0; c < kGroup; ++c) acc[c] = 0;
+  const uint8_t* base = g.X + grp * kGroup * g.ldb;
+  const int64_t nch = g.nchunks();
+  for (int64_t ch = 0; ch < nch; ++ch) {
+    const int64_t row0 = ch * (kWave * RPL) + (int64_t)lane * RPL;
+    double th[RPL];
+    load_vec<RPL, double>(tp, row0, th);
+#pragma unroll
+    for (int c = 0; c < kGroup; ++c) {
+      double x[RPL];
+      load_rows<FMT, RPL, double>(base + c * g.ldb, row0, x);
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) acc[c] = fma(x[r], th[r], acc[c]);
+    }
+  }
+  const double dot = reduce16(acc, lane);
+  const int64_t j = grp * kGroup + group_col_of_lane(lane);
+  const bool owner = (lane & 3) == 0;
+  const double vj = (dot - cm[j] * sum_tp[0]) * cinv[j];
+  const double lam = clam[j];
+  double ratio = 0.0;
+  if (cinv[j] != 0.0) ratio = lam > 0.0 ? fabs(vj) / lam : (vj != 0.0 ? INFINITY : 0.0);
+  if (owner && v) v[j] = vj;
+  ratio = wave_max(owner ? ratio : 0.0);
+  if (lane == 0) gmax[grp] = ratio;
+}
+
+template <int FMT, int RPL>
+static void dots64_fmt(const Geom& g, const double* tp, const double* sum_tp, const double* cm,
+                       const double* cinv, const double* clam, double* v, double* gmax,
+                       hipStream_t s) {
+  hipLaunchKernelGGL((k_dots64<FMT, RPL>), dim3((unsigned)((g.ngroups() + 3) / 4)), dim3(256), 0,
+                     s, g, tp, sum_tp, cm, cinv, clam, v, gmax);
+}
+
+#define PQR_DISPATCH64(FN, ...)                                          \
+  switch (g.fmt * 2 + (g.rpl == 16)) {                                   \
+    case F64 * 2: FN<F64, 4>(__VA_ARGS__); break;                        \
+    case F64 * 2 + 1: FN<F64, 16>(__VA_ARGS__); break;                   \
+    case F32 * 2: FN<F32, 4>(__VA_ARGS__); break;                        \
+    case F32 * 2 + 1: FN<F32, 16>(__VA_ARGS__); break;                   \
+    case BF16 * 2: FN<BF16, 4>(__VA_ARGS__); break;                      \
+    case BF16 * 2 + 1: FN<BF16, 16>(__VA_ARGS__); break;                 \
+    case FP8 * 2: FN<FP8, 4>(__VA_ARGS__); break;                        \
+    case FP8 * 2 + 1: FN<FP8, 16>(__VA_ARGS__); break;                   \
+    case I8 * 2: FN<I8, 4>(__VA_ARGS__); break;                          \
+    case I8 * 2 + 1: FN<I8, 16>(__VA_ARGS__); break;                     \
+    case B2 * 2 + 1: FN<B2, 16>(__VA_ARGS__); break;                     \
+    default: return hipErrorInvalidValue;                                \
+  }
+
+hipError_t launch_dots64(const Geom& g, const double* theta_p, const double* sum_tp,
+                         const double* cm, const double* cinv, const double* clam, double* v,
+                         double* gmax, hipStream_t s) {
+  PQR_DISPATCH64(dots64_fmt, g, theta_p, sum_tp, cm, cinv, clam, v, gmax, s)
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Sparse s = X~ beta (FP64) over the active list, as in the iteration.
+__device__ __forceinline__ int splits_in_use64(int count, int smax, int min_per) {
+  const int s = (count + min_per - 1) / min_per;
+  return s < 1 ? 1 : (s > smax ? smax : s);
+}
+
+template <int FMT, int RPL>
+__global__ __launch_bounds__(256) void k_axpy64(Geom g, CertBufs c, int smax, int min_per) {
+  const int lane = threadIdx.x & 63;
+  const int64_t ch = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int split = blockIdx.y;
+  const int count = c.ctl->count;
+  const int seff = splits_in_use64(count, smax, min_per);
+  if (split >= seff || ch >= g.nchunks()) return;
+  const int per = (count + seff - 1) / seff;
+  const int e0 = split * per;
+  const int e1 = e0 + per < count ? e0 + per : count;
+  const int64_t row0 = ch * (kWave * RPL) + (int64_t)lane * RPL;
+  double acc[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) acc[r] = 0;
+  double off = 0;
+  for (int e = e0; e < e1; ++e) {
+    const int64_t grp = c.list[e];
+    for (int k = 0; k < kGroup; ++k) {
+      const int64_t j = grp * kGroup + k;
+      const double bj = c.beta_d[j] * c.cinv[j];
+      if (bj != 0.0) {
+        double x[RPL];
+        load_rows<FMT, RPL, double>(g.X + j * g.ldb, row0, x);
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) acc[r] = fma(x[r], bj, acc[r]);
+        off = fma(c.cm[j], bj, off);
+      }
+    }
+  }
+  double* out = c.partial + (int64_t)split * g.n_pad + row0;
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) out[r] = acc[r] - off;
+}
+
+// Per-row pinball loss of r = y - s - beta0 into block partials.
+__global__ __launch_bounds__(256) void k_loss64(CertBufs c, int64_t n, int64_t n_pad, double tau,
+                                                int smax, int min_per) {
+  __shared__ double red[4];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int seff = splits_in_use64(c.ctl->count, smax, min_per);
+  double q[1] = {0.0};
+  if (i < n) {
+    double s = c.ctl->beta0;
+    for (int k = 0; k < seff; ++k) s += c.partial[(int64_t)k * n_pad + i];
+    const double r = c.y[i] - s;
+    q[0] = (r < 0 ? tau - 1.0 : tau) * r;
+  }
+  block_sum<256, 1, double>(q, red);
+  if (threadIdx.x == 0) c.bpart[blockIdx.x] = q[0];
+}
+
+__global__ __launch_bounds__(256) void k_penalty64(const double* __restrict__ beta,
+                                                   const double* __restrict__ clam, int64_t p,
+                                                   double* bpart) {
+  __shared__ double red[4];
+  double q[1] = {0.0};
+  const int64_t per = (p + gridDim.x - 1) / gridDim.x;
+  const int64_t j0 = (int64_t)blockIdx.x * per, j1 = j0 + per < p ? j0 + per : p;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += 256) q[0] += clam[j] * fabs(beta[j]);
+  block_sum<256, 1, double>(q, red);
+  if (threadIdx.x == 0) bpart[blockIdx.x] = q[0];
+}
+
+__global__ __launch_bounds__(256) void k_final_sum(const double* bpart, int64_t m, double scale,
+                                                   double* out) {
+  __shared__ double red[4];
+  double q[1] = {0.0};
+  for (int64_t k = threadIdx.x; k < m; k += 256) q[0] += bpart[k];
+  block_sum<256, 1, double>(q, red);
+  if (threadIdx.x == 0) *out = q[0] * scale;
+}
+
+template <int FMT, int RPL>
+static void axpy64_fmt(const Geom& g, const CertBufs& c, int smax, int min_per, hipStream_t s) {
+  hipLaunchKernelGGL((k_axpy64<FMT, RPL>), dim3((unsigned)((g.nchunks() + 3) / 4), smax),
+                     dim3(256), 0, s, g, c, smax, min_per);
+}
+
+hipError_t launch_primal64(const Geom& g, const CertBufs& c, double tau, int smax, int min_per,
+                           hipStream_t s) {
+  PQR_DISPATCH64(axpy64_fmt, g, c, smax, min_per, s)
+  const unsigned nb = (unsigned)(g.n_pad / 256);
+  hipLaunchKernelGGL(k_loss64, dim3(nb), dim3(256), 0, s, c, g.n, g.n_pad, tau, smax, min_per);
+  hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(256), 0, s, c.bpart, (int64_t)nb,
+                     1.0 / (double)g.n, c.out + 0);
+  const unsigned np = 512;
+  hipLaunchKernelGGL(k_penalty64, dim3(np), dim3(256), 0, s, c.beta_d, c.clam, g.p_pad,
+                     c.bpart + nb);
+  hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(256), 0, s, c.bpart + nb, (int64_t)np, 1.0,
+                     c.out + 1);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_stage_sum(const double* a, int64_t m, double* bpart) {
+  __shared__ double red[4];
+  double q[1] = {0.0};
+  const int64_t per = (m + gridDim.x - 1) / gridDim.x;
+  const int64_t j0 = (int64_t)blockIdx.x * per, j1 = j0 + per < m ? j0 + per : m;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += 256) q[0] += a[j];
+  block_sum<256, 1, double>(q, red);
+  if (threadIdx.x == 0) bpart[blockIdx.x] = q[0];
+}
+
+__global__ __launch_bounds__(256) void k_stage_max(const double* a, int64_t m, double* bpart) {
+  double mx = 0.0;
+  const int64_t per = (m + gridDim.x - 1) / gridDim.x;
+  const int64_t j0 = (int64_t)blockIdx.x * per, j1 = j0 + per < m ? j0 + per : m;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += 256) mx = fmax(mx, a[j]);
+  __shared__ double red[4];
+  mx = wave_max(mx);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) bpart[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+__global__ __launch_bounds__(256) void k_final_max(const double* bpart, int64_t m, double* out) {
+  double mx = 0.0;
+  for (int64_t k = threadIdx.x; k < m; k += 256) mx = fmax(mx, bpart[k]);
+  __shared__ double red[4];
+  mx = wave_max(mx);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+hipError_t launch_reduce_sum(const double* a, int64_t m, double* bpart, double* out,
+                             hipStream_t s) {
+  const unsigned nb = 256;
+  hipLaunchKernelGGL(k_stage_sum, dim3(nb), dim3(256), 0, s, a, m, bpart);
+  hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(256), 0, s, bpart, (int64_t)nb, 1.0, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_max(const double* a, int64_t m, double* bpart, double* out,
+                             hipStream_t s) {
+  const unsigned nb = 256;
+  hipLaunchKernelGGL(k_stage_max, dim3(nb), dim3(256), 0, s, a, m, bpart);
+  hipLaunchKernelGGL(k_final_max, dim3(1), dim3(256), 0, s, bpart, (int64_t)nb, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+template <typename S, typename D>
+__global__ __launch_bounds__(256) void k_convert(const S* a, int64_t m, D* out) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256)
+    out[i] = (D)a[i];
+}
+
+template <typename T>
+hipError_t launch_to_double(const T* a, int64_t m, double* out, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert<T, double>), dim3(1024), dim3(256), 0, s, a, m, out);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_from_double(const double* a, int64_t m, T* out, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert<double, T>), dim3(1024), dim3(256), 0, s, a, m, out);
+  return hipGetLastError();
+}
+template hipError_t launch_to_double<float>(const float*, int64_t, double*, hipStream_t);
+template hipError_t launch_to_double<double>(const double*, int64_t, double*, hipStream_t);
+template hipError_t launch_from_double<float>(const double*, int64_t, float*, hipStream_t);
+template hipError_t launch_from_double<double>(const double*, int64_t, double*, hipStream_t);
+
+}  // namespace pqr

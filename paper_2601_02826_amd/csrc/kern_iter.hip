@@ -1,0 +1,323 @@
+// One iteration of FS-QRPPA (Algorithm 1) on gfx950, as four kernels:
+//
+//   k_sweep    v = X~^T theta for every column (one wavefront per 16-column
+//              group, the design read once) fused with the per-block
+//              weighted soft threshold of eq. beta_update.
+//   k_compact  one workgroup: the ordered list of column groups holding a
+//              nonzero coefficient, the sweep's norm partials, and the
+//              intercept (lambda_0 = 0, so its update is a plain step).
+//   k_axpy     s = X~ beta^{k+1} over the nonzero coefficients only: the
+//              partial products X_g beta_g of the paper, gathered by column
+//              and reduced in a fixed order (no atomics).
+//   k_update   the z prox of eq. z_update, the extrapolated dual step of
+//              eq. fsppa_update, and the norms of the iteration (including
+//              the H-norm successive difference), reduced by the last block.
+#include "pqr_kernels.h"
+
+namespace pqr {
+
+template <typename T> __device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
+
+template <int FMT, int RPL, typename T>
+__device__ __forceinline__ void group_dots(const Geom& g, int64_t grp, const T* __restrict__ theta,
+                                           T (&acc)[kGroup]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int c = 0; c < kGroup; ++c) acc[c] = 0;
+  const uint8_t* base = g.X + grp * kGroup * g.ldb;
+  const int64_t nch = g.nchunks();
+  for (int64_t ch = 0; ch < nch; ++ch) {
+    const int64_t row0 = ch * (kWave * RPL) + (int64_t)lane * RPL;
+    T th[RPL];
+    load_vec<RPL, T>(theta, row0, th);
+#pragma unroll
+    for (int c = 0; c < kGroup; ++c) {
+      T x[RPL];
+      load_rows<FMT, RPL, T>(base + c * g.ldb, row0, x);
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) acc[c] = fma(x[r], th[r], acc[c]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <int FMT, int RPL, typename T>
+__global__ __launch_bounds__(256) void k_sweep(Geom g, IterBufs<T> b) {
+  const int lane = threadIdx.x & 63;
+  const int64_t grp = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (grp >= g.ngroups()) return;
+  T acc[kGroup];
+  group_dots<FMT, RPL, T>(g, grp, b.theta, acc);
+  const T dot = reduce16(acc, lane);
+
+  const int64_t j = grp * kGroup + group_col_of_lane(lane);
+  const bool owner = (lane & 3) == 0;
+  const T st = (T)b.ctl->sum_theta;
+  const T v = (dot - b.cm[j] * st) * b.cinv[j];   // x~_j^T theta on the standardized scale
+  const T bo = b.beta[j];
+  const T eta = b.geta[grp];
+  const T lam = b.clam[j];
+  const T a = eta * bo + v;
+  const T bn = (tmax<T>(a - lam, 0) - tmax<T>(-a - lam, 0)) / eta;   // eq. beta_update
+  if (owner) b.beta[j] = bn;
+  const T d = bn - bo;
+  T q0 = owner ? d * d : T(0);
+  T q1 = owner ? bn * bn : T(0);
+  T q2 = owner ? eta * d * d : T(0);
+  T q3 = owner ? b.cm[j] * b.cinv[j] * bn : T(0);
+  const unsigned long long nz = __ballot(owner && bn != T(0));
+  q0 = wave_sum(q0); q1 = wave_sum(q1); q2 = wave_sum(q2); q3 = wave_sum(q3);
+  if (lane == 0) {
+    T* o = b.gnorm + grp * 4;
+    o[0] = q0; o[1] = q1; o[2] = q2; o[3] = q3;
+    b.gflag[grp] = nz != 0ull;
+  }
+}
+
+// Flags only (for a warm start): group has a nonzero coefficient.
+template <typename T>
+__global__ __launch_bounds__(256) void k_flags(int64_t ngroups, IterBufs<T> b) {
+  const int64_t grp = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (grp >= ngroups) return;
+  int f = 0;
+  for (int c = 0; c < kGroup; ++c) f |= b.beta[grp * kGroup + c] != T(0);
+  b.gflag[grp] = f;
+  T* o = b.gnorm + grp * 4;
+  o[0] = o[1] = o[2] = o[3] = 0;
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(1024) void k_compact(int64_t ngroups, IterBufs<T> b, double eta0,
+                                                  int step_intercept) {
+  __shared__ int scan[1024];
+  __shared__ double red[4 * 16];
+  const int t = threadIdx.x;
+  const int64_t per = (ngroups + 1023) / 1024;
+  const int64_t g0 = t * per, g1 = g0 + per < ngroups ? g0 + per : ngroups;
+  int cnt = 0;
+  double s[4] = {0, 0, 0, 0};
+  for (int64_t gi = g0; gi < g1; ++gi) {
+    cnt += b.gflag[gi] != 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s[k] += (double)b.gnorm[gi * 4 + k];
+  }
+  scan[t] = cnt;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int v = t >= off ? scan[t - off] : 0;
+    __syncthreads();
+    scan[t] += v;
+    __syncthreads();
+  }
+  int pos = scan[t] - cnt;
+  for (int64_t gi = g0; gi < g1; ++gi)
+    if (b.gflag[gi]) b.list[pos++] = (int)gi;
+  const int total = scan[1023];
+  block_sum<1024, 4, double>(s, red);
+  if (t == 0) {
+    Ctl* c = b.ctl;
+    double b0 = c->beta0, b0n = b0;
+    if (step_intercept) b0n = b0 + c->sum_theta / eta0;   // intercept: lambda_0 = 0
+    const double d0 = b0n - b0;
+    c->beta0 = b0n;
+    c->nb[0] = s[0] + d0 * d0;
+    c->nb[1] = s[1] + b0n * b0n;
+    c->nb[2] = s[2] + eta0 * d0 * d0;
+    c->nb[3] = s[3];
+    c->count = total;
+  }
+}
+
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int splits_in_use(int count, int smax, int min_per) {
+  const int s = (count + min_per - 1) / min_per;
+  return s < 1 ? 1 : (s > smax ? smax : s);
+}
+
+template <int FMT, int RPL, typename T>
+__global__ __launch_bounds__(256) void k_axpy(Geom g, IterBufs<T> b, int smax, int min_per) {
+  const int lane = threadIdx.x & 63;
+  const int64_t ch = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int split = blockIdx.y;
+  const int count = b.ctl->count;
+  const int seff = splits_in_use(count, smax, min_per);
+  if (split >= seff || ch >= g.nchunks()) return;
+  const int per = (count + seff - 1) / seff;
+  const int e0 = split * per;
+  const int e1 = e0 + per < count ? e0 + per : count;
+  const int64_t row0 = ch * (kWave * RPL) + (int64_t)lane * RPL;
+  T acc[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) acc[r] = 0;
+  T off = 0;
+  for (int e = e0; e < e1; ++e) {
+    const int64_t grp = b.list[e];
+    for (int c = 0; c < kGroup; ++c) {
+      const int64_t j = grp * kGroup + c;
+      const T bj = b.beta[j] * b.cinv[j];   // coefficient on the raw column
+      if (bj != T(0)) {
+        T x[RPL];
+        load_rows<FMT, RPL, T>(g.X + j * g.ldb, row0, x);
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) acc[r] = fma(x[r], bj, acc[r]);
+        off = fma(b.cm[j], bj, off);
+      }
+    }
+  }
+  T* out = b.partial + (int64_t)split * g.n_pad + row0;
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) out[r] = acc[r] - off;
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_update(IterBufs<T> b, IterParams ip, int64_t n,
+                                                int64_t n_pad) {
+  __shared__ double red[8 * 4];
+  __shared__ int last;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int seff = splits_in_use(b.ctl->count, ip.smax, ip.min_per);
+  double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (i < n) {
+    T s = (T)b.ctl->beta0;
+    for (int k = 0; k < seff; ++k) s += b.partial[(int64_t)k * n_pad + i];
+    const T mu = (T)ip.mu;
+    const T zo = b.z[i], to = b.theta[i], ro = b.r[i];
+    const T u = zo + to / mu;
+    const T zn = tmax<T>(u - (T)(ip.tau / ((double)n * ip.mu)), 0) -
+                 tmax<T>(-u - (T)((1.0 - ip.tau) / ((double)n * ip.mu)), 0);   // eq. z_update
+    const T rn = s + zn - b.y[i];
+    const T tn = to - (T)ip.sigma * ((T)2 * rn - ro);                         // dual step
+    b.z[i] = zn;
+    b.theta[i] = tn;
+    b.r[i] = rn;
+    const double dz = (double)zn - (double)zo, dt = (double)tn - (double)to;
+    q[0] = dz * dz; q[1] = (double)zn * zn; q[2] = dt * dt; q[3] = (double)tn * tn;
+    q[4] = (double)rn * rn; q[5] = dt * ((double)rn - (double)ro); q[6] = (double)tn;
+  }
+  block_sum<256, 8, double>(q, red);
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 8; ++k) b.bpart[(int64_t)blockIdx.x * 8 + k] = q[k];
+    __threadfence();
+    const unsigned prev = atomicAdd(&b.ctl->blocks_done, 1u);
+    last = prev == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  if (threadIdx.x < 8) {
+    double s = 0;
+    for (unsigned blk = 0; blk < gridDim.x; ++blk) s += b.bpart[blk * 8 + threadIdx.x];
+    red[threadIdx.x] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Ctl* c = b.ctl;
+    for (int k = 0; k < 8; ++k) c->nr[k] = red[k];
+    c->sum_theta = red[6];
+    const double delta = c->nb[2] + ip.mu * red[0] + 2.0 * red[5] + ((ip.G + 1.0) / ip.mu) * red[2];
+    c->delta_prev = c->delta;
+    c->delta = delta;
+    c->n_increase = (c->iter > 0 && delta > c->delta_prev * (1.0 + 1e-6) && delta > 1e-300)
+                        ? c->n_increase + 1 : 0;
+    c->iter += 1;
+    c->blocks_done = 0u;
+  }
+}
+
+// r = X~beta + beta0 + z - y and sum(theta) for a given state.
+template <typename T>
+__global__ __launch_bounds__(256) void k_init_r(IterBufs<T> b, IterParams ip, int64_t n,
+                                                int64_t n_pad) {
+  __shared__ double red[8 * 4];
+  __shared__ int last;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int seff = splits_in_use(b.ctl->count, ip.smax, ip.min_per);
+  double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (i < n) {
+    T s = (T)b.ctl->beta0;
+    for (int k = 0; k < seff; ++k) s += b.partial[(int64_t)k * n_pad + i];
+    b.r[i] = s + b.z[i] - b.y[i];
+    q[6] = (double)b.theta[i];
+  }
+  block_sum<256, 8, double>(q, red);
+  if (threadIdx.x == 0) {
+    b.bpart[(int64_t)blockIdx.x * 8 + 6] = q[6];
+    __threadfence();
+    const unsigned prev = atomicAdd(&b.ctl->blocks_done, 1u);
+    last = prev == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  if (threadIdx.x == 0) {
+    double s = 0;
+    for (unsigned blk = 0; blk < gridDim.x; ++blk) s += b.bpart[blk * 8 + 6];
+    b.ctl->sum_theta = s;
+    b.ctl->blocks_done = 0u;
+    b.ctl->delta = 0;
+    b.ctl->delta_prev = 0;
+    b.ctl->n_increase = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <int FMT, int RPL, typename T>
+static void launch_fmt(const Geom& g, const IterBufs<T>& b, const IterParams& ip, hipStream_t s) {
+  const int64_t ng = g.ngroups();
+  hipLaunchKernelGGL((k_sweep<FMT, RPL, T>), dim3((unsigned)((ng + 3) / 4)), dim3(256), 0, s, g, b);
+  hipLaunchKernelGGL((k_compact<T>), dim3(1), dim3(1024), 0, s, ng, b, ip.eta0, 1);
+  hipLaunchKernelGGL((k_axpy<FMT, RPL, T>), dim3((unsigned)((g.nchunks() + 3) / 4), ip.smax),
+                     dim3(256), 0, s, g, b, ip.smax, ip.min_per);
+  hipLaunchKernelGGL((k_update<T>), dim3((unsigned)(g.n_pad / 256)), dim3(256), 0, s, b, ip, g.n,
+                     g.n_pad);
+}
+
+template <int FMT, int RPL, typename T>
+static void prepare_fmt(const Geom& g, const IterBufs<T>& b, const IterParams& ip, hipStream_t s) {
+  const int64_t ng = g.ngroups();
+  hipLaunchKernelGGL((k_flags<T>), dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, s, ng, b);
+  hipLaunchKernelGGL((k_compact<T>), dim3(1), dim3(1024), 0, s, ng, b, ip.eta0, 0);
+  hipLaunchKernelGGL((k_axpy<FMT, RPL, T>), dim3((unsigned)((g.nchunks() + 3) / 4), ip.smax),
+                     dim3(256), 0, s, g, b, ip.smax, ip.min_per);
+  hipLaunchKernelGGL((k_init_r<T>), dim3((unsigned)(g.n_pad / 256)), dim3(256), 0, s, b, ip, g.n,
+                     g.n_pad);
+}
+
+#define PQR_DISPATCH(FN, ...)                                                       \
+  switch (g.fmt * 2 + (g.rpl == 16)) {                                              \
+    case F64 * 2: FN<F64, 4, T>(__VA_ARGS__); break;                                \
+    case F64 * 2 + 1: FN<F64, 16, T>(__VA_ARGS__); break;                           \
+    case F32 * 2: FN<F32, 4, T>(__VA_ARGS__); break;                                \
+    case F32 * 2 + 1: FN<F32, 16, T>(__VA_ARGS__); break;                           \
+    case BF16 * 2: FN<BF16, 4, T>(__VA_ARGS__); break;                              \
+    case BF16 * 2 + 1: FN<BF16, 16, T>(__VA_ARGS__); break;                         \
+    case FP8 * 2: FN<FP8, 4, T>(__VA_ARGS__); break;                                \
+    case FP8 * 2 + 1: FN<FP8, 16, T>(__VA_ARGS__); break;                           \
+    case I8 * 2: FN<I8, 4, T>(__VA_ARGS__); break;                                  \
+    case I8 * 2 + 1: FN<I8, 16, T>(__VA_ARGS__); break;                             \
+    case B2 * 2 + 1: FN<B2, 16, T>(__VA_ARGS__); break;                             \
+    default: return hipErrorInvalidValue;                                           \
+  }
+
+template <typename T>
+hipError_t launch_iteration(const Geom& g, const IterBufs<T>& b, const IterParams& ip,
+                            hipStream_t s) {
+  PQR_DISPATCH(launch_fmt, g, b, ip, s)
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prepare_state(const Geom& g, const IterBufs<T>& b, const IterParams& ip,
+                                hipStream_t s) {
+  PQR_DISPATCH(prepare_fmt, g, b, ip, s)
+  return hipGetLastError();
+}
+
+template hipError_t launch_iteration<float>(const Geom&, const IterBufs<float>&, const IterParams&, hipStream_t);
+template hipError_t launch_iteration<double>(const Geom&, const IterBufs<double>&, const IterParams&, hipStream_t);
+template hipError_t launch_prepare_state<float>(const Geom&, const IterBufs<float>&, const IterParams&, hipStream_t);
+template hipError_t launch_prepare_state<double>(const Geom&, const IterBufs<double>&, const IterParams&, hipStream_t);
+
+}  // namespace pqr

@@ -1,0 +1,805 @@
+// libpqr C ABI: context, set-up (encode, column statistics, block step sizes)
+// and the FS-QRPPA driver (Algorithm 1) with its FP64 stopping certificate.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pqr.h"
+#include "pqr_kernels.h"
+
+using namespace pqr;
+
+struct pqr_ctx {
+  std::string err;
+  Geom g{};
+  int standardize = 1;
+  pqr_options opt{};
+  hipStream_t s = nullptr;
+  int G = 0;
+  std::vector<int> bounds;      // feature-column boundaries of the blocks (G+1)
+  std::vector<int> gbound;      // group boundaries of the blocks (G+1)
+  std::vector<double> Lambda;   // Lambda_max(X~_g^T X~_g) estimates
+  int smax = 256, min_per = 4;
+
+  // design and column parameters
+  uint8_t* X = nullptr;
+  double *cm_d = nullptr, *cinv_d = nullptr, *sd_d = nullptr;
+  float *cm_f = nullptr, *cinv_f = nullptr;
+  int* iota = nullptr;
+
+  // iteration state (type given by opt.iter_prec)
+  void *beta = nullptr, *clam_t = nullptr, *geta_t = nullptr, *gnorm = nullptr,
+       *partial = nullptr, *y_t = nullptr, *z = nullptr, *theta = nullptr, *r = nullptr,
+       *cm_t = nullptr, *cinv_t = nullptr;
+  int *gflag = nullptr, *list = nullptr;
+  double* bpart = nullptr;
+  Ctl* ctl = nullptr;
+  Ctl* ctl_kkt = nullptr;
+
+  // certificate buffers (FP64)
+  double *y_d = nullptr, *theta_p = nullptr, *beta_d = nullptr, *clam_d = nullptr, *v_d = nullptr,
+         *gpart = nullptr, *partial64 = nullptr, *bpart64 = nullptr, *out_d = nullptr,
+         *scratch64 = nullptr, *bt_out = nullptr;
+  int64_t bpart64_len = 0;
+  double* out_h = nullptr;   // pinned
+
+  bool have_state = false;
+  double state_mu = 0.0;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+#define HIPCHK(expr)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);               \
+      return PQR_ERR_DEVICE;                                                      \
+    }                                                                             \
+  } while (0)
+
+template <typename P>
+pqr_status dalloc(pqr_ctx* ctx, P** p, size_t bytes) {
+  void* q = nullptr;
+  if (hipMalloc(&q, bytes < 256 ? 256 : bytes) != hipSuccess) {
+    ctx->err = "hipMalloc of " + std::to_string(bytes) + " bytes failed";
+    (void)hipGetLastError();
+    return PQR_ERR_OOM;
+  }
+  ctx->allocs.push_back(q);
+  *p = static_cast<P*>(q);
+  return PQR_OK;
+}
+
+#define TRY(expr)                  \
+  do {                             \
+    pqr_status st_ = (expr);       \
+    if (st_ != PQR_OK) return st_; \
+  } while (0)
+
+int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+bool finite_all(const double* a, int64_t m) {
+  for (int64_t i = 0; i < m; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+// Largest eigenvalue of the symmetric tridiagonal (alpha, beta) by cyclic
+// Jacobi on the dense matrix, plus the Lanczos residual bound |beta_k s_k|.
+double ritz_upper(const double* alpha, const double* beta, int k) {
+  std::vector<double> A((size_t)k * k, 0.0), V((size_t)k * k, 0.0);
+  for (int i = 0; i < k; ++i) {
+    A[i * k + i] = alpha[i];
+    V[i * k + i] = 1.0;
+    if (i + 1 < k) A[i * k + i + 1] = A[(i + 1) * k + i] = beta[i];
+  }
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < k; ++i)
+      for (int j = i + 1; j < k; ++j) off += A[i * k + j] * A[i * k + j];
+    if (off < 1e-30) break;
+    for (int pi = 0; pi < k; ++pi)
+      for (int qi = pi + 1; qi < k; ++qi) {
+        const double apq = A[pi * k + qi];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double app = A[pi * k + pi], aqq = A[qi * k + qi];
+        const double th = 0.5 * (aqq - app) / apq;
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int m = 0; m < k; ++m) {
+          const double amp = A[m * k + pi], amq = A[m * k + qi];
+          A[m * k + pi] = c * amp - s * amq;
+          A[m * k + qi] = s * amp + c * amq;
+        }
+        for (int m = 0; m < k; ++m) {
+          const double apm = A[pi * k + m], aqm = A[qi * k + m];
+          A[pi * k + m] = c * apm - s * aqm;
+          A[qi * k + m] = s * apm + c * aqm;
+        }
+        for (int m = 0; m < k; ++m) {
+          const double vmp = V[m * k + pi], vmq = V[m * k + qi];
+          V[m * k + pi] = c * vmp - s * vmq;
+          V[m * k + qi] = s * vmp + c * vmq;
+        }
+      }
+  }
+  int best = 0;
+  for (int i = 1; i < k; ++i)
+    if (A[i * k + i] > A[best * k + best]) best = i;
+  const double resid = std::fabs(beta[k - 1] * V[(k - 1) * k + best]);
+  return A[best * k + best] + resid;
+}
+
+template <typename T>
+IterBufs<T> bufs(pqr_ctx* ctx) {
+  IterBufs<T> b;
+  b.beta = (T*)ctx->beta;
+  b.cm = (const T*)ctx->cm_t;
+  b.cinv = (const T*)ctx->cinv_t;
+  b.clam = (const T*)ctx->clam_t;
+  b.geta = (const T*)ctx->geta_t;
+  b.gnorm = (T*)ctx->gnorm;
+  b.gflag = ctx->gflag;
+  b.list = ctx->list;
+  b.partial = (T*)ctx->partial;
+  b.y = (const T*)ctx->y_t;
+  b.z = (T*)ctx->z;
+  b.theta = (T*)ctx->theta;
+  b.r = (T*)ctx->r;
+  b.bpart = ctx->bpart;
+  b.ctl = ctx->ctl;
+  return b;
+}
+
+size_t tsize(const pqr_ctx* ctx) { return ctx->opt.iter_prec == PQR_ITER_F64 ? 8 : 4; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+extern "C" void pqr_default_options(pqr_options* o) {
+  std::memset(o, 0, sizeof(*o));
+  o->mu = 0.0;
+  o->mu_scale = 0.1;
+  o->G = 48;
+  o->eta_margin = 0.01;
+  o->lanczos_steps = 40;
+  o->iter_prec = PQR_ITER_F32;
+  o->tol_gap = 1e-6;
+  o->cert_every = 50;
+  o->max_iter = 1000000;
+  o->stream = nullptr;
+}
+
+extern "C" const char* pqr_status_string(pqr_status s) {
+  switch (s) {
+    case PQR_OK: return "ok";
+    case PQR_ERR_INVALID_ARG: return "invalid argument";
+    case PQR_ERR_OOM: return "out of device memory";
+    case PQR_ERR_DEVICE: return "device error";
+    case PQR_ERR_NOT_CONVERGED: return "not converged";
+    case PQR_ERR_DIVERGED: return "diverged";
+    case PQR_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown";
+}
+
+extern "C" const char* pqr_last_error(const pqr_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+extern "C" void pqr_destroy(pqr_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->s) (void)hipStreamSynchronize(ctx->s);
+  else (void)hipDeviceSynchronize();
+  for (void* p : ctx->allocs) (void)hipFree(p);
+  if (ctx->out_h) (void)hipHostFree(ctx->out_h);
+  delete ctx;
+}
+
+static pqr_status create_impl(pqr_ctx* ctx, const pqr_design* X) {
+  const int64_t n = X->n, p = X->p;
+  Geom& g = ctx->g;
+  g.fmt = X->store_fmt;
+  g.rpl = (g.fmt == B2 || n >= 8192) ? 16 : 4;
+  g.n = n;
+  g.n_pad = round_up(n, (int64_t)kWave * g.rpl);
+  g.p = p;
+  g.p_pad = round_up(p, kGroup);
+  g.ldb = round_up(fmt_col_bytes(g.fmt, g.n_pad), 256);
+  ctx->standardize = X->standardize ? 1 : 0;
+  hipStream_t s = ctx->s;
+  const int64_t ng = g.ngroups();
+  if (g.n_pad / 256 + 1024 > (int64_t)1 << 22) {
+    ctx->err = "n too large";
+    return PQR_ERR_UNSUPPORTED;
+  }
+
+  TRY(dalloc(ctx, &ctx->X, (size_t)(g.p_pad * g.ldb)));
+  g.X = ctx->X;
+  HIPCHK(launch_encode(X->data, X->src_fmt, X->ld, g, ctx->X, s));
+
+  double *sum, *sumsq;
+  TRY(dalloc(ctx, &sum, g.p_pad * 8));
+  TRY(dalloc(ctx, &sumsq, g.p_pad * 8));
+  TRY(dalloc(ctx, &ctx->cm_d, g.p_pad * 8));
+  TRY(dalloc(ctx, &ctx->cinv_d, g.p_pad * 8));
+  TRY(dalloc(ctx, &ctx->sd_d, g.p_pad * 8));
+  TRY(dalloc(ctx, &ctx->cm_f, g.p_pad * 4));
+  TRY(dalloc(ctx, &ctx->cinv_f, g.p_pad * 4));
+  HIPCHK(launch_colstats(g, sum, sumsq, s));
+  HIPCHK(launch_colparams(sum, sumsq, n, p, g.p_pad, ctx->standardize, ctx->cm_d, ctx->cinv_d,
+                          ctx->sd_d, ctx->cm_f, ctx->cinv_f, s));
+
+  // blocks: contiguous near-equal runs of 16-column groups, intercept in block 0
+  int G = ctx->opt.G > 0 ? ctx->opt.G : 48;
+  if (G > ng) G = (int)ng;
+  ctx->G = G;
+  ctx->gbound.resize(G + 1);
+  ctx->bounds.resize(G + 1);
+  for (int b = 0; b < G; ++b) ctx->gbound[b] = (int)(((int64_t)b * ng) / G);
+  ctx->gbound[G] = (int)ng;
+  for (int b = 0; b <= G; ++b)
+    ctx->bounds[b] = (int)std::min<int64_t>(p, (int64_t)kGroup * ctx->gbound[b]);
+  ctx->bounds[G] = (int)p;
+  std::vector<int> gblock(ng);
+  for (int b = 0; b < G; ++b)
+    for (int q = ctx->gbound[b]; q < ctx->gbound[b + 1]; ++q) gblock[q] = b;
+  int *gblock_d, *bstart_d;
+  TRY(dalloc(ctx, &gblock_d, ng * 4));
+  TRY(dalloc(ctx, &bstart_d, (G + 1) * 4));
+  HIPCHK(hipMemcpyAsync(gblock_d, gblock.data(), ng * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(bstart_d, ctx->gbound.data(), (G + 1) * 4, hipMemcpyHostToDevice, s));
+  std::vector<int> iota(ng);
+  for (int64_t q = 0; q < ng; ++q) iota[q] = (int)q;
+  TRY(dalloc(ctx, &ctx->iota, ng * 4));
+  HIPCHK(hipMemcpyAsync(ctx->iota, iota.data(), ng * 4, hipMemcpyHostToDevice, s));
+
+  // Lanczos estimates of Lambda_max(X~_g^T X~_g), all blocks together
+  const int T = std::max(2, ctx->opt.lanczos_steps > 0 ? ctx->opt.lanczos_steps : 40);
+  const int splits = 8;
+  float *q, *qprev, *wbuf, *qsum, *u, *lpart;
+  double *al, *be;
+  TRY(dalloc(ctx, &q, (size_t)G * g.n_pad * 4));
+  TRY(dalloc(ctx, &qprev, (size_t)G * g.n_pad * 4));
+  TRY(dalloc(ctx, &wbuf, (size_t)G * g.n_pad * 4));
+  TRY(dalloc(ctx, &qsum, G * 4));
+  TRY(dalloc(ctx, &u, g.p_pad * 4));
+  TRY(dalloc(ctx, &lpart, (size_t)G * splits * g.n_pad * 4));
+  TRY(dalloc(ctx, &al, (size_t)G * T * 8));
+  TRY(dalloc(ctx, &be, (size_t)G * T * 8));
+  HIPCHK(launch_lanczos_init(n, g.n_pad, G, q, qprev, qsum, s));
+  for (int k = 0; k < T; ++k) {
+    HIPCHK(launch_block_dots(g, q, g.n_pad, gblock_d, ctx->cm_f, ctx->cinv_f, qsum, u, s));
+    HIPCHK(launch_block_axpy(g, u, ctx->cm_f, ctx->cinv_f, bstart_d, G, splits, lpart, s));
+    HIPCHK(launch_lanczos_step(n, g.n_pad, G, splits, k, T, lpart, q, qprev, wbuf, qsum, al, be, s));
+  }
+  std::vector<double> ha((size_t)G * T), hb((size_t)G * T);
+  HIPCHK(hipMemcpyAsync(ha.data(), al, ha.size() * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hb.data(), be, hb.size() * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  ctx->Lambda.resize(G);
+  for (int b = 0; b < G; ++b) {
+    int k = T;
+    for (int i = 0; i < T; ++i)
+      if (hb[(size_t)b * T + i] < 1e-12 * std::max(1.0, std::fabs(ha[(size_t)b * T]))) { k = i + 1; break; }
+    ctx->Lambda[b] = std::max(ritz_upper(&ha[(size_t)b * T], &hb[(size_t)b * T], k), 1e-30);
+  }
+
+  // iteration buffers
+  const size_t ts = tsize(ctx);
+  TRY(dalloc(ctx, &ctx->beta, g.p_pad * ts));
+  TRY(dalloc(ctx, &ctx->clam_t, g.p_pad * ts));
+  TRY(dalloc(ctx, &ctx->cm_t, g.p_pad * ts));
+  TRY(dalloc(ctx, &ctx->cinv_t, g.p_pad * ts));
+  TRY(dalloc(ctx, &ctx->geta_t, ng * ts));
+  TRY(dalloc(ctx, &ctx->gnorm, ng * 4 * ts));
+  TRY(dalloc(ctx, &ctx->gflag, ng * 4));
+  TRY(dalloc(ctx, &ctx->list, ng * 4));
+  TRY(dalloc(ctx, &ctx->partial, (size_t)ctx->smax * g.n_pad * ts));
+  TRY(dalloc(ctx, &ctx->y_t, g.n_pad * ts));
+  TRY(dalloc(ctx, &ctx->z, g.n_pad * ts));
+  TRY(dalloc(ctx, &ctx->theta, g.n_pad * ts));
+  TRY(dalloc(ctx, &ctx->r, g.n_pad * ts));
+  TRY(dalloc(ctx, &ctx->bpart, (g.n_pad / 256) * 8 * 8));
+  TRY(dalloc(ctx, &ctx->ctl, sizeof(Ctl)));
+  TRY(dalloc(ctx, &ctx->ctl_kkt, sizeof(Ctl)));
+  HIPCHK(hipMemsetAsync(ctx->beta, 0, g.p_pad * ts, s));
+  HIPCHK(hipMemsetAsync(ctx->ctl, 0, sizeof(Ctl), s));
+  if (ts == 8) {
+    HIPCHK(hipMemcpyAsync(ctx->cm_t, ctx->cm_d, g.p_pad * 8, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(ctx->cinv_t, ctx->cinv_d, g.p_pad * 8, hipMemcpyDeviceToDevice, s));
+  } else {
+    HIPCHK(hipMemcpyAsync(ctx->cm_t, ctx->cm_f, g.p_pad * 4, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(ctx->cinv_t, ctx->cinv_f, g.p_pad * 4, hipMemcpyDeviceToDevice, s));
+  }
+
+  // certificate buffers
+  TRY(dalloc(ctx, &ctx->y_d, g.n_pad * 8));
+  TRY(dalloc(ctx, &ctx->theta_p, g.n_pad * 8));
+  TRY(dalloc(ctx, &ctx->scratch64, std::max(g.n_pad, g.p_pad + 1) * 8));
+  TRY(dalloc(ctx, &ctx->beta_d, g.p_pad * 8));
+  TRY(dalloc(ctx, &ctx->bt_out, (g.p_pad + 1) * 8));
+  TRY(dalloc(ctx, &ctx->clam_d, g.p_pad * 8));
+  TRY(dalloc(ctx, &ctx->v_d, g.p_pad * 8));
+  TRY(dalloc(ctx, &ctx->gpart, ng * 8));
+  TRY(dalloc(ctx, &ctx->partial64, (size_t)ctx->smax * g.n_pad * 8));
+  ctx->bpart64_len = std::max<int64_t>(g.n_pad / 256 + 1024, g.p_pad + 1024);
+  TRY(dalloc(ctx, &ctx->bpart64, ctx->bpart64_len * 8));
+  TRY(dalloc(ctx, &ctx->out_d, 16 * 8));
+  if (hipHostMalloc((void**)&ctx->out_h, 16 * 8, hipHostMallocDefault) != hipSuccess) {
+    ctx->err = "hipHostMalloc failed";
+    return PQR_ERR_OOM;
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  return PQR_OK;
+}
+
+extern "C" pqr_status pqr_create(pqr_ctx** out, const pqr_design* X, const pqr_options* opt) {
+  if (!out) return PQR_ERR_INVALID_ARG;
+  *out = nullptr;
+  pqr_ctx* ctx = new pqr_ctx();
+  if (opt) ctx->opt = *opt; else pqr_default_options(&ctx->opt);
+  pqr_options d;
+  pqr_default_options(&d);
+  if (ctx->opt.mu_scale <= 0) ctx->opt.mu_scale = d.mu_scale;
+  if (ctx->opt.eta_margin <= 0) ctx->opt.eta_margin = d.eta_margin;
+  if (ctx->opt.tol_gap <= 0) ctx->opt.tol_gap = d.tol_gap;
+  if (ctx->opt.cert_every <= 0) ctx->opt.cert_every = d.cert_every;
+  if (ctx->opt.max_iter <= 0) ctx->opt.max_iter = d.max_iter;
+  if (ctx->opt.iter_prec != PQR_ITER_F64) ctx->opt.iter_prec = PQR_ITER_F32;
+  ctx->s = (hipStream_t)ctx->opt.stream;
+  *out = ctx;
+  if (!X || !X->data || X->n < 1 || X->p < 1 || X->ld < X->n) {
+    ctx->err = "invalid design: need data, n >= 1, p >= 1, ld >= n";
+    return PQR_ERR_INVALID_ARG;
+  }
+  const bool src_int = X->src_fmt == PQR_X_I8;
+  const bool src_flt = X->src_fmt == PQR_X_F64 || X->src_fmt == PQR_X_F32;
+  if (!src_int && !src_flt) {
+    ctx->err = "src_fmt must be PQR_X_F64, PQR_X_F32 or PQR_X_I8";
+    return PQR_ERR_INVALID_ARG;
+  }
+  if (X->store_fmt < PQR_X_F64 || X->store_fmt > PQR_X_2BIT) {
+    ctx->err = "unknown store_fmt";
+    return PQR_ERR_INVALID_ARG;
+  }
+  if (src_flt && !(X->store_fmt == PQR_X_F64 || X->store_fmt == PQR_X_F32 ||
+                   X->store_fmt == PQR_X_BF16)) {
+    ctx->err = "floating-point designs can be stored as F64, F32 or BF16 only";
+    return PQR_ERR_UNSUPPORTED;
+  }
+  if (X->p > ((int64_t)1 << 31) - 64 || X->n > ((int64_t)1 << 31) - 4096) {
+    ctx->err = "n or p too large";
+    return PQR_ERR_UNSUPPORTED;
+  }
+  pqr_status st = create_impl(ctx, X);
+  return st;
+}
+
+// ---------------------------------------------------------------------------
+namespace {
+
+struct SolveSetup {
+  double tau, mu, sigma;
+  IterParams ip;
+};
+
+template <typename T>
+pqr_status upload_problem(pqr_ctx* ctx, const double* y, double tau, double lambda,
+                          const double* weights, double* lmax_out, double* score) {
+  const Geom& g = ctx->g;
+  hipStream_t s = ctx->s;
+  // y
+  std::vector<double> yh(g.n_pad, 0.0);
+  std::memcpy(yh.data(), y, g.n * 8);
+  HIPCHK(hipMemcpyAsync(ctx->y_d, yh.data(), g.n_pad * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(launch_set_y<T>(ctx->y_d, g.n, g.n_pad, (T*)ctx->y_t, s));
+  // weights (lambda = 1) for lambda_max, then lambda * w
+  std::vector<double> lh(g.p_pad, 0.0);
+  for (int64_t j = 0; j < g.p; ++j) lh[j] = weights ? weights[1 + j] : 1.0;
+  HIPCHK(hipMemcpyAsync(ctx->clam_d, lh.data(), g.p_pad * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(launch_null_dual(ctx->y_d, g.n, g.n_pad, tau, ctx->theta_p, ctx->out_d, s));
+  HIPCHK(launch_dots64(g, ctx->theta_p, ctx->out_d + 5, ctx->cm_d, ctx->cinv_d, ctx->clam_d,
+                       ctx->v_d, ctx->gpart, s));
+  HIPCHK(launch_reduce_max(ctx->gpart, g.ngroups(), ctx->bpart64, ctx->out_d + 3, s));
+  HIPCHK(hipMemcpyAsync(ctx->out_h, ctx->out_d, 16 * 8, hipMemcpyDeviceToHost, s));
+  if (score) HIPCHK(hipMemcpyAsync(score, ctx->v_d, g.p * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (lmax_out) *lmax_out = ctx->out_h[3];
+  for (int64_t j = 0; j < g.p; ++j) lh[j] *= lambda;
+  HIPCHK(hipMemcpyAsync(ctx->clam_d, lh.data(), g.p_pad * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(launch_from_double<T>(ctx->clam_d, g.p_pad, (T*)ctx->clam_t, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return PQR_OK;
+}
+
+pqr_status validate_problem(pqr_ctx* ctx, const double* y, double tau, double lambda,
+                            const double* weights) {
+  if (!y) { ctx->err = "y is NULL"; return PQR_ERR_INVALID_ARG; }
+  if (!(tau > 0.0 && tau < 1.0)) { ctx->err = "tau must lie in (0, 1)"; return PQR_ERR_INVALID_ARG; }
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) {
+    ctx->err = "lambda must be finite and >= 0";
+    return PQR_ERR_INVALID_ARG;
+  }
+  if (!finite_all(y, ctx->g.n)) { ctx->err = "y has non-finite entries"; return PQR_ERR_INVALID_ARG; }
+  if (weights) {
+    for (int64_t j = 1; j <= ctx->g.p; ++j)
+      if (!(weights[j] >= 0.0) || !std::isfinite(weights[j])) {
+        ctx->err = "weights must be finite and >= 0";
+        return PQR_ERR_INVALID_ARG;
+      }
+  }
+  return PQR_OK;
+}
+
+template <typename T>
+pqr_status set_eta(pqr_ctx* ctx, double mu, const double* eta_explicit, double eta_scale,
+                   IterParams& ip, double tau) {
+  const Geom& g = ctx->g;
+  std::vector<double> eta(ctx->G);
+  for (int b = 0; b < ctx->G; ++b)
+    eta[b] = eta_explicit ? eta_explicit[b]
+                          : eta_scale * (1.0 + ctx->opt.eta_margin) * mu * ctx->Lambda[b];
+  std::vector<T> ge(g.ngroups());
+  for (int b = 0; b < ctx->G; ++b)
+    for (int q = ctx->gbound[b]; q < ctx->gbound[b + 1]; ++q) ge[q] = (T)eta[b];
+  HIPCHK(hipMemcpyAsync(ctx->geta_t, ge.data(), ge.size() * sizeof(T), hipMemcpyHostToDevice, ctx->s));
+  HIPCHK(hipStreamSynchronize(ctx->s));
+  ip.tau = tau;
+  ip.mu = mu;
+  ip.sigma = mu / (ctx->G + 1.0);
+  ip.eta0 = eta[0];
+  ip.G = ctx->G;
+  ip.smax = ctx->smax;
+  ip.min_per = ctx->min_per;
+  return PQR_OK;
+}
+
+// Load (beta_std, z, theta) from host, or a zero start; then rebuild r.
+template <typename T>
+pqr_status init_state(pqr_ctx* ctx, int start, const double* beta_std, const double* zh,
+                      const double* th, const IterParams& ip) {
+  const Geom& g = ctx->g;
+  hipStream_t s = ctx->s;
+  Ctl c;
+  std::memset(&c, 0, sizeof(c));
+  if (start == PQR_START_DEVICE) {
+    HIPCHK(hipMemcpyAsync(&c, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double b0 = c.beta0;
+    std::memset(&c, 0, sizeof(c));
+    c.beta0 = b0;
+  } else if (start == PQR_START_HOST) {
+    std::vector<double> tmp(std::max(g.n_pad, g.p_pad), 0.0);
+    std::memcpy(tmp.data(), beta_std + 1, g.p * 8);
+    std::fill(tmp.begin() + g.p, tmp.end(), 0.0);
+    HIPCHK(hipMemcpyAsync(ctx->scratch64, tmp.data(), g.p_pad * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(launch_from_double<T>(ctx->scratch64, g.p_pad, (T*)ctx->beta, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::fill(tmp.begin(), tmp.end(), 0.0);
+    std::memcpy(tmp.data(), zh, g.n * 8);
+    HIPCHK(hipMemcpyAsync(ctx->scratch64, tmp.data(), g.n_pad * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(launch_from_double<T>(ctx->scratch64, g.n_pad, (T*)ctx->z, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::fill(tmp.begin(), tmp.end(), 0.0);
+    std::memcpy(tmp.data(), th, g.n * 8);
+    HIPCHK(hipMemcpyAsync(ctx->scratch64, tmp.data(), g.n_pad * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(launch_from_double<T>(ctx->scratch64, g.n_pad, (T*)ctx->theta, s));
+    HIPCHK(hipStreamSynchronize(s));
+    c.beta0 = beta_std[0];
+  } else {
+    HIPCHK(hipMemsetAsync(ctx->beta, 0, g.p_pad * sizeof(T), s));
+    HIPCHK(hipMemcpyAsync(ctx->z, ctx->y_t, g.n_pad * sizeof(T), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemsetAsync(ctx->theta, 0, g.n_pad * sizeof(T), s));
+  }
+  HIPCHK(hipMemcpyAsync(ctx->ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, s));
+  HIPCHK(launch_prepare_state<T>(g, bufs<T>(ctx), ip, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return PQR_OK;
+}
+
+struct Cert {
+  double primal, dual, gap, rel_gap, maxratio;
+};
+
+template <typename T>
+pqr_status certificate(pqr_ctx* ctx, double tau, Cert* out) {
+  const Geom& g = ctx->g;
+  hipStream_t s = ctx->s;
+  HIPCHK(launch_project<T>((const T*)ctx->theta, g.n, g.n_pad, tau, ctx->y_d, ctx->theta_p,
+                           ctx->out_d, s));
+  HIPCHK(launch_dots64(g, ctx->theta_p, ctx->out_d + 5, ctx->cm_d, ctx->cinv_d, ctx->clam_d,
+                       nullptr, ctx->gpart, s));
+  HIPCHK(launch_reduce_max(ctx->gpart, g.ngroups(), ctx->bpart64, ctx->out_d + 3, s));
+  HIPCHK(launch_to_double<T>((const T*)ctx->beta, g.p_pad, ctx->beta_d, s));
+  CertBufs c{};
+  c.y = ctx->y_d;
+  c.theta_p = ctx->theta_p;
+  c.beta_d = ctx->beta_d;
+  c.cm = ctx->cm_d;
+  c.cinv = ctx->cinv_d;
+  c.clam = ctx->clam_d;
+  c.partial = ctx->partial64;
+  c.list = ctx->list;
+  c.ctl = ctx->ctl;
+  c.bpart = ctx->bpart64;
+  c.out = ctx->out_d;
+  HIPCHK(launch_primal64(g, c, tau, ctx->smax, ctx->min_per, s));
+  HIPCHK(hipMemcpyAsync(ctx->out_h, ctx->out_d, 16 * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const double* o = ctx->out_h;
+  const double mr = o[3];
+  const double alpha = mr > 1.0 ? (std::isinf(mr) ? 0.0 : 1.0 / mr) : 1.0;
+  out->primal = o[0] + o[1];
+  out->dual = alpha * o[2];
+  out->gap = out->primal - out->dual;
+  out->rel_gap = out->gap / std::max(std::fabs(out->primal), 1e-300);
+  out->maxratio = mr;
+  return PQR_OK;
+}
+
+template <typename T>
+pqr_status export_state(pqr_ctx* ctx, pqr_result* res) {
+  const Geom& g = ctx->g;
+  hipStream_t s = ctx->s;
+  Ctl c;
+  HIPCHK(hipMemcpyAsync(&c, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  HIPCHK(launch_to_double<T>((const T*)ctx->beta, g.p_pad, ctx->beta_d, s));
+  std::vector<double> b(g.p);
+  HIPCHK(hipMemcpyAsync(b.data(), ctx->beta_d, g.p * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  int64_t nnz = 0;
+  for (int64_t j = 0; j < g.p; ++j) nnz += b[j] != 0.0;
+  res->nnz = nnz;
+  if (res->beta_std) {
+    res->beta_std[0] = c.beta0;
+    std::memcpy(res->beta_std + 1, b.data(), g.p * 8);
+  }
+  if (res->beta) {
+    // scratch64 holds [beta0, beta_std(1..p)] for the back-transform
+    std::vector<double> bs(g.p + 1);
+    bs[0] = c.beta0;
+    std::memcpy(bs.data() + 1, b.data(), g.p * 8);
+    HIPCHK(hipMemcpyAsync(ctx->scratch64, bs.data(), (g.p + 1) * 8, hipMemcpyHostToDevice, s));
+    double* bo = ctx->bt_out;
+    HIPCHK(launch_back_transform(ctx->scratch64, g.p, ctx->cm_d, ctx->cinv_d, c.beta0, bo,
+                                 ctx->bpart64, s));
+    HIPCHK(hipMemcpyAsync(res->beta, bo, (g.p + 1) * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  if (res->z) {
+    HIPCHK(launch_to_double<T>((const T*)ctx->z, g.n_pad, ctx->scratch64, s));
+    HIPCHK(hipMemcpyAsync(res->z, ctx->scratch64, g.n * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  if (res->theta) {
+    HIPCHK(launch_to_double<T>((const T*)ctx->theta, g.n_pad, ctx->scratch64, s));
+    HIPCHK(hipMemcpyAsync(res->theta, ctx->scratch64, g.n * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  return PQR_OK;
+}
+
+double default_mu(const pqr_ctx* ctx, const double* y) {
+  const int64_t n = ctx->g.n;
+  double m = 0.0;
+  for (int64_t i = 0; i < n; ++i) m += y[i];
+  m /= (double)n;
+  double v = 0.0;
+  for (int64_t i = 0; i < n; ++i) v += (y[i] - m) * (y[i] - m);
+  const double sd = std::sqrt(v / (double)n);
+  return ctx->opt.mu_scale * std::sqrt(ctx->G + 1.0) / ((double)n * (sd > 0 ? sd : 1.0));
+}
+
+template <typename T>
+pqr_status solve_impl(pqr_ctx* ctx, const double* y, double tau, double lambda,
+                      const double* weights, int start, const pqr_result* warm, pqr_result* out) {
+  const auto t0 = std::chrono::steady_clock::now();
+  TRY(validate_problem(ctx, y, tau, lambda, weights));
+  if (start == PQR_START_HOST && (!warm || !warm->beta_std || !warm->z || !warm->theta)) {
+    ctx->err = "PQR_START_HOST needs warm->beta_std, warm->z and warm->theta";
+    return PQR_ERR_INVALID_ARG;
+  }
+  if (start == PQR_START_DEVICE && !ctx->have_state) {
+    ctx->err = "PQR_START_DEVICE needs a previous solve on this context";
+    return PQR_ERR_INVALID_ARG;
+  }
+  double lmax = 0.0;
+  TRY(upload_problem<T>(ctx, y, tau, lambda, weights, &lmax, nullptr));
+  const double mu = ctx->opt.mu > 0 ? ctx->opt.mu
+                                    : (start == PQR_START_DEVICE ? ctx->state_mu : default_mu(ctx, y));
+  IterParams ip{};
+  double eta_scale = 1.0;
+  TRY(set_eta<T>(ctx, mu, nullptr, eta_scale, ip, tau));
+  TRY(init_state<T>(ctx, start, warm ? warm->beta_std : nullptr, warm ? warm->z : nullptr,
+                    warm ? warm->theta : nullptr, ip));
+  ctx->have_state = true;
+  ctx->state_mu = mu;
+
+  const Geom& g = ctx->g;
+  hipStream_t s = ctx->s;
+  int64_t it = 0, certs = 0, restarts = 0;
+  Cert cert{};
+  pqr_status status = PQR_ERR_NOT_CONVERGED;
+  TRY(certificate<T>(ctx, tau, &cert));
+  ++certs;
+  if (cert.rel_gap <= ctx->opt.tol_gap) status = PQR_OK;
+  while (status != PQR_OK && it < ctx->opt.max_iter) {
+    const int64_t chunk = std::min<int64_t>(ctx->opt.cert_every, ctx->opt.max_iter - it);
+    const IterBufs<T> b = bufs<T>(ctx);
+    for (int64_t k = 0; k < chunk; ++k) HIPCHK(launch_iteration<T>(g, b, ip, s));
+    it += chunk;
+    Ctl c;
+    HIPCHK(hipMemcpyAsync(&c, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (!std::isfinite(c.delta) || c.n_increase > 25) {
+      // the H-norm successive difference grows: the metric is not positive
+      // definite (eta_g below mu Lambda_max); double eta and restart
+      if (++restarts > 2) {
+        ctx->err = "H-norm monitor: successive differences keep growing after doubling eta twice";
+        status = PQR_ERR_DIVERGED;
+        break;
+      }
+      eta_scale *= 2.0;
+      TRY(set_eta<T>(ctx, mu, nullptr, eta_scale, ip, tau));
+      TRY(init_state<T>(ctx, PQR_START_ZERO, nullptr, nullptr, nullptr, ip));
+      continue;
+    }
+    TRY(certificate<T>(ctx, tau, &cert));
+    ++certs;
+    if (cert.rel_gap <= ctx->opt.tol_gap) status = PQR_OK;
+  }
+  if (out) {
+    TRY(export_state<T>(ctx, out));
+    out->iters = it;
+    out->certs = certs;
+    out->x_passes = it + certs + 1;
+    out->primal = cert.primal;
+    out->dual = cert.dual;
+    out->rel_gap = cert.rel_gap;
+    out->lambda_max = lmax;
+    out->mu = mu;
+    out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (status == PQR_ERR_NOT_CONVERGED)
+    ctx->err = "max_iter reached with relative gap " + std::to_string(cert.rel_gap);
+  return status;
+}
+
+}  // namespace
+
+extern "C" pqr_status pqr_solve(pqr_ctx* ctx, const double* y, double tau, double lambda,
+                                const double* weights, int start, const pqr_result* warm,
+                                pqr_result* out) {
+  if (!ctx) return PQR_ERR_INVALID_ARG;
+  if (start < PQR_START_ZERO || start > PQR_START_DEVICE) {
+    ctx->err = "unknown start mode";
+    return PQR_ERR_INVALID_ARG;
+  }
+  if (ctx->opt.iter_prec == PQR_ITER_F64)
+    return solve_impl<double>(ctx, y, tau, lambda, weights, start, warm, out);
+  return solve_impl<float>(ctx, y, tau, lambda, weights, start, warm, out);
+}
+
+namespace {
+template <typename T>
+pqr_status iterate_impl(pqr_ctx* ctx, const double* y, double tau, double lambda,
+                        const double* weights, double mu, const double* eta, int64_t iters,
+                        double* beta_std, double* z, double* theta) {
+  TRY(validate_problem(ctx, y, tau, lambda, weights));
+  if (!(mu > 0) || !eta || !beta_std || !z || !theta || iters < 0) {
+    ctx->err = "pqr_iterate needs mu > 0, eta, beta_std, z, theta and iters >= 0";
+    return PQR_ERR_INVALID_ARG;
+  }
+  for (int b = 0; b < ctx->G; ++b)
+    if (!(eta[b] > 0) || !std::isfinite(eta[b])) {
+      ctx->err = "eta must be positive";
+      return PQR_ERR_INVALID_ARG;
+    }
+  TRY(upload_problem<T>(ctx, y, tau, lambda, weights, nullptr, nullptr));
+  IterParams ip{};
+  TRY(set_eta<T>(ctx, mu, eta, 1.0, ip, tau));
+  TRY(init_state<T>(ctx, PQR_START_HOST, beta_std, z, theta, ip));
+  const IterBufs<T> b = bufs<T>(ctx);
+  for (int64_t k = 0; k < iters; ++k) HIPCHK(launch_iteration<T>(ctx->g, b, ip, ctx->s));
+  HIPCHK(hipStreamSynchronize(ctx->s));
+  ctx->have_state = true;
+  ctx->state_mu = mu;
+  pqr_result r{};
+  r.beta_std = beta_std;
+  r.z = z;
+  r.theta = theta;
+  return export_state<T>(ctx, &r);
+}
+}  // namespace
+
+extern "C" pqr_status pqr_iterate(pqr_ctx* ctx, const double* y, double tau, double lambda,
+                                  const double* weights, double mu, const double* eta,
+                                  int64_t iters, double* beta_std, double* z, double* theta) {
+  if (!ctx) return PQR_ERR_INVALID_ARG;
+  if (ctx->opt.iter_prec == PQR_ITER_F64)
+    return iterate_impl<double>(ctx, y, tau, lambda, weights, mu, eta, iters, beta_std, z, theta);
+  return iterate_impl<float>(ctx, y, tau, lambda, weights, mu, eta, iters, beta_std, z, theta);
+}
+
+extern "C" pqr_status pqr_kkt(pqr_ctx* ctx, const double* y, double tau, double lambda,
+                              const double* weights, const double* beta_std, const double* theta,
+                              double rep[4]) {
+  if (!ctx) return PQR_ERR_INVALID_ARG;
+  TRY(validate_problem(ctx, y, tau, lambda, weights));
+  if (!beta_std || !theta || !rep) {
+    ctx->err = "pqr_kkt needs beta_std, theta and rep";
+    return PQR_ERR_INVALID_ARG;
+  }
+  const Geom& g = ctx->g;
+  hipStream_t s = ctx->s;
+  // only the FP64 buffers and the kkt control block are touched
+  std::vector<double> yh(g.n_pad, 0.0);
+  std::memcpy(yh.data(), y, g.n * 8);
+  HIPCHK(hipMemcpyAsync(ctx->y_d, yh.data(), g.n_pad * 8, hipMemcpyHostToDevice, s));
+  std::vector<double> lh(g.p_pad, 0.0);
+  for (int64_t j = 0; j < g.p; ++j) lh[j] = lambda * (weights ? weights[1 + j] : 1.0);
+  HIPCHK(hipMemcpyAsync(ctx->clam_d, lh.data(), g.p_pad * 8, hipMemcpyHostToDevice, s));
+  std::vector<double> bh(g.p_pad, 0.0);
+  std::memcpy(bh.data(), beta_std + 1, g.p * 8);
+  HIPCHK(hipMemcpyAsync(ctx->beta_d, bh.data(), g.p_pad * 8, hipMemcpyHostToDevice, s));
+  std::vector<double> th(g.n_pad, 0.0);
+  std::memcpy(th.data(), theta, g.n * 8);
+  HIPCHK(hipMemcpyAsync(ctx->scratch64, th.data(), g.n_pad * 8, hipMemcpyHostToDevice, s));
+  Ctl c;
+  std::memset(&c, 0, sizeof(c));
+  c.count = (int)g.ngroups();
+  c.beta0 = beta_std[0];
+  HIPCHK(hipMemcpyAsync(ctx->ctl_kkt, &c, sizeof(Ctl), hipMemcpyHostToDevice, s));
+  HIPCHK(launch_project<double>(ctx->scratch64, g.n, g.n_pad, tau, ctx->y_d, ctx->theta_p,
+                                ctx->out_d, s));
+  HIPCHK(launch_dots64(g, ctx->theta_p, ctx->out_d + 5, ctx->cm_d, ctx->cinv_d, ctx->clam_d,
+                       nullptr, ctx->gpart, s));
+  HIPCHK(launch_reduce_max(ctx->gpart, g.ngroups(), ctx->bpart64, ctx->out_d + 3, s));
+  CertBufs cb{};
+  cb.y = ctx->y_d;
+  cb.theta_p = ctx->theta_p;
+  cb.beta_d = ctx->beta_d;
+  cb.cm = ctx->cm_d;
+  cb.cinv = ctx->cinv_d;
+  cb.clam = ctx->clam_d;
+  cb.partial = ctx->partial64;
+  cb.list = ctx->iota;
+  cb.ctl = ctx->ctl_kkt;
+  cb.bpart = ctx->bpart64;
+  cb.out = ctx->out_d;
+  HIPCHK(launch_primal64(g, cb, tau, ctx->smax, ctx->min_per, s));
+  HIPCHK(hipMemcpyAsync(ctx->out_h, ctx->out_d, 16 * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const double* o = ctx->out_h;
+  const double mr = o[3];
+  const double alpha = mr > 1.0 ? (std::isinf(mr) ? 0.0 : 1.0 / mr) : 1.0;
+  rep[0] = o[0] + o[1];
+  rep[1] = alpha * o[2];
+  rep[2] = (rep[0] - rep[1]) / std::max(std::fabs(rep[0]), 1e-300);
+  rep[3] = mr;
+  return PQR_OK;
+}
+
+extern "C" pqr_status pqr_lambda_max(pqr_ctx* ctx, const double* y, double tau,
+                                     const double* weights, double* lambda_max, double* score) {
+  if (!ctx) return PQR_ERR_INVALID_ARG;
+  TRY(validate_problem(ctx, y, tau, 0.0, weights));
+  if (ctx->opt.iter_prec == PQR_ITER_F64)
+    return upload_problem<double>(ctx, y, tau, 0.0, weights, lambda_max, score);
+  return upload_problem<float>(ctx, y, tau, 0.0, weights, lambda_max, score);
+}
+
+extern "C" pqr_status pqr_blocks(pqr_ctx* ctx, int* G, int* bounds, double* Lambda) {
+  if (!ctx) return PQR_ERR_INVALID_ARG;
+  if (G) *G = ctx->G;
+  if (bounds) std::memcpy(bounds, ctx->bounds.data(), (ctx->G + 1) * sizeof(int));
+  if (Lambda) std::memcpy(Lambda, ctx->Lambda.data(), ctx->G * sizeof(double));
+  return PQR_OK;
+}

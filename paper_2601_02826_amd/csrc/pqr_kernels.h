@@ -1,0 +1,135 @@
+// Kernel launchers of libpqr (host-callable, plain types only).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pqr_dev.h"
+
+namespace pqr {
+
+// Geometry of the design store shared by every kernel.
+struct Geom {
+  const uint8_t* X;   // store base
+  int fmt;            // Fmt
+  int rpl;            // rows per lane: 4 or 16
+  int64_t n, n_pad;   // rows, padded rows (multiple of 64*rpl)
+  int64_t p, p_pad;   // feature columns, padded to a multiple of kGroup
+  int64_t ldb;        // bytes per stored column
+  __host__ __device__ int64_t ngroups() const { return p_pad / kGroup; }
+  __host__ __device__ int64_t nchunks() const { return n_pad / (kWave * rpl); }
+};
+
+template <typename T>
+struct IterBufs {
+  T* beta;        // p_pad, solver scale, in place
+  const T* cm;    // p_pad column means (0 when not standardized)
+  const T* cinv;  // p_pad 1/s_j (0 for excluded and padding columns)
+  const T* clam;  // p_pad lambda_j
+  const T* geta;  // ngroups: eta of the block holding each group
+  T* gnorm;       // ngroups x 4 sweep partials
+  int* gflag;     // ngroups: 1 if any coefficient of the group is nonzero
+  int* list;      // ngroups: active groups in increasing order (first ctl->count)
+  T* partial;     // smax x n_pad partial products
+  const T* y;     // n_pad
+  T* z;           // n_pad
+  T* theta;       // n_pad (padding rows stay 0)
+  T* r;           // n_pad cached residual X~beta + z - y
+  double* bpart;  // update-kernel block partials (nblk x 8)
+  Ctl* ctl;
+};
+
+struct IterParams {
+  double tau, mu, sigma, eta0;
+  int G;
+  int smax, min_per;
+};
+
+// One FS-QRPPA iteration = sweep, compact, axpy, update.
+template <typename T>
+hipError_t launch_iteration(const Geom& g, const IterBufs<T>& b, const IterParams& ip,
+                            hipStream_t s);
+
+// Recompute the cached residual r = X~beta + beta0 + z - y and sum(theta) for a
+// given state (after a warm start); also rebuilds the active list.
+template <typename T>
+hipError_t launch_prepare_state(const Geom& g, const IterBufs<T>& b, const IterParams& ip,
+                                hipStream_t s);
+
+// ---- FP64 certificate ----
+struct CertBufs {
+  const double* y;      // n_pad
+  double* theta_p;      // n_pad projected theta
+  double* beta_d;       // p_pad coefficients in double
+  const double* cm;     // p_pad
+  const double* cinv;   // p_pad
+  const double* clam;   // p_pad
+  double* v;            // p_pad (optional output of x~_j^T theta')
+  double* gpart;        // ngroups partials
+  double* partial;      // smax x n_pad
+  const int* list;      // active groups
+  const Ctl* ctl;       // count and beta0
+  double* bpart;        // reduction scratch (>= n_pad/256 + 1024 doubles)
+  double* out;          // 8 doubles: [primal loss, penalty, y.theta', max ratio, shift, sum theta', -, -]
+};
+
+// theta' = clip(theta - c, (tau-1)/n, tau/n) with sum theta' = 0 (bisection on c).
+template <typename T>
+hipError_t launch_project(const T* theta, int64_t n, int64_t n_pad, double tau, const double* y,
+                          double* theta_p, double* out, hipStream_t s);
+
+// v_j = x~_j^T theta' in FP64 for all columns; per-group max |v_j| / lambda_j.
+hipError_t launch_dots64(const Geom& g, const double* theta_p, const double* sum_tp,
+                         const double* cm, const double* cinv, const double* clam, double* v,
+                         double* gmax, hipStream_t s);
+
+// Sparse s = X~ beta over the active list in FP64, then P(beta) pieces.
+hipError_t launch_primal64(const Geom& g, const CertBufs& c, double tau, int smax, int min_per,
+                           hipStream_t s);
+
+// Deterministic reductions into out[k]: sum / max of a device array.
+hipError_t launch_reduce_sum(const double* a, int64_t m, double* bpart, double* out, hipStream_t s);
+hipError_t launch_reduce_max(const double* a, int64_t m, double* bpart, double* out, hipStream_t s);
+
+template <typename T>
+hipError_t launch_to_double(const T* a, int64_t m, double* out, hipStream_t s);
+template <typename T>
+hipError_t launch_from_double(const double* a, int64_t m, T* out, hipStream_t s);
+
+// ---- setup ----
+hipError_t launch_encode(const void* src, int src_fmt, int64_t ld, const Geom& g, uint8_t* dst,
+                         hipStream_t s);
+// column sums and sums of squares in double (exact for integer codes)
+hipError_t launch_colstats(const Geom& g, double* sum, double* sumsq, hipStream_t s);
+
+// Lanczos building blocks: u_j = x~_j^T q_{block(j)} for all columns, and the
+// per-block dense products w_g = X~_g u_g into partials.
+hipError_t launch_block_dots(const Geom& g, const float* q, int64_t qstride, const int* gblock,
+                             const float* cm, const float* cinv, const float* qsum, float* u,
+                             hipStream_t s);
+hipError_t launch_block_axpy(const Geom& g, const float* u, const float* cm, const float* cinv,
+                             const int* bstart, int G, int splits, float* partial, hipStream_t s);
+hipError_t launch_lanczos_step(int64_t n, int64_t n_pad, int G, int splits, int k, int T,
+                               const float* partial, float* q, float* qprev, float* wbuf,
+                               float* qsum, double* alpha, double* beta, hipStream_t s);
+hipError_t launch_lanczos_init(int64_t n, int64_t n_pad, int G, float* q, float* qprev,
+                               float* qsum, hipStream_t s);
+
+// tau-quantile of y (k-th order statistic, k = ceil(n tau)) and the null dual
+// psi/n written to theta_p; out[0] = q.
+hipError_t launch_null_dual(const double* y, int64_t n, int64_t n_pad, double tau,
+                            double* theta_p, double* out, hipStream_t s);
+
+// back-transform: beta_orig_j = beta_j * cinv_j, beta_orig_0 = beta0 - sum_j m_j beta_orig_j
+hipError_t launch_back_transform(const double* beta_std, int64_t p, const double* cm,
+                                 const double* cinv, double beta0, double* beta_orig,
+                                 double* bpart, hipStream_t s);
+
+}  // namespace pqr
+
+namespace pqr {
+hipError_t launch_colparams(const double* sum, const double* sumsq, int64_t n, int64_t p,
+                            int64_t p_pad, int standardize, double* cm_d, double* cinv_d,
+                            double* sd_d, float* cm_f, float* cinv_f, hipStream_t s);
+template <typename T>
+hipError_t launch_set_y(const double* y, int64_t n, int64_t n_pad, T* y_t, hipStream_t s);
+}  // namespace pqr
