@@ -1,0 +1,245 @@
+#!/usr/bin/env python3
+"""Benchmark: time-to-KKT-tolerance per PQR solve on the genotype workload
+(n = 20,000 samples, p = 1,000,000 dosage columns stored as int8), GPU vs the
+plain FP64 oracle.
+
+One step = the whole hot path over the workload: the 20-point lambda path
+lambda_t = lambda_max * 0.01^((t-1)/19), t = 1..20, at tau = 0.5, each point
+solved by FS-QRPPA to a certified relative duality gap <= --tol and warm-started
+from the previous point on the device (set-up, i.e. encoding, column statistics
+and the Lanczos step sizes, happens once before timing).  `value` is solves per
+second (20 solves per step); the JSON line also carries the time-to-KKT per
+solve, X-passes/s, the live roofline of the sweep kernel (HIP events on the
+solver's stream) and the oracle timed on the host cores.
+
+    python bench.py [--steps K] [--warmup W] [--fmt i8|2bit|fp8|bf16] [--tol 1e-3]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-KKT-tol per PQR solve + HBM GB/s, genotype n=20k p=1M, GPU vs plain"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER = {"i8": 1.0, "fp8": 1.0, "2bit": 0.25, "bf16": 2.0, "f32": 4.0}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--fmt", default="i8", choices=sorted(BYTES_PER))
+    ap.add_argument("--tol", type=float, default=1e-2)
+    ap.add_argument("--G", type=int, default=12)
+    ap.add_argument("--npath", type=int, default=20)
+    ap.add_argument("--max-iter", type=int, default=3000)
+    ap.add_argument("--cert-every", type=int, default=50)
+    ap.add_argument("--n", type=int, default=20_000)
+    ap.add_argument("--p", type=int, default=1_000_000)
+    ap.add_argument("--cpu-cols", type=int, default=8000,
+                    help="columns in the oracle's timing sample (0 = skip the CPU baseline)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
+                    help="before timing, copy a buffer of this many MiB once (a plain copy "
+                         "kernel of known size for scaling the HBM byte counters)")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("kern_iter.hip", "pqr_dev.h"):
+        with open(os.path.join(ROOT, "paper_2601_02826_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(fmt, n, p):
+    """HBM bytes per sweep launch from the committed rocprofv3 --pmc summary,
+    if it was taken on the current sweep kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"sweep_{fmt}_{n // 1000}kx{p // 1000}k_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_source_sha") != source_hash():
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
+def make_workload(n, p):
+    import numpy as np
+    import torch
+    from datagen import native
+    from datagen.configs import GenotypeSpec, make_genotype
+    spec = GenotypeSpec(n=n, p=p, n_causal=200, seed=3, tag=3, tau=0.5)
+    g = make_genotype(spec, with_X=False)
+    thr = torch.from_numpy(g["thr"].astype(np.int64)).to(torch.int32).cuda()
+    Xc = torch.empty((p, n), dtype=torch.uint8, device="cuda")
+    native.genotype_device(Xc.data_ptr(), n, n, p, thr.data_ptr(), spec.seed, spec.tag,
+                           torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    return spec, g, Xc
+
+
+def run_path(ctx, y, lams):
+    recs = []
+    for k, lam in enumerate(lams):
+        r = ctx.solve(y, 0.5, lam, start="zero" if k == 0 else "device",
+                      allow_not_converged=True)
+        recs.append(r)
+        log(f"  lambda[{k}]={lam:.4g}: iters={r['iters']} rel_gap={r['rel_gap']:.2e} "
+            f"nnz={r['nnz']} {r['seconds']:.2f}s")
+    return recs
+
+
+def cpu_baseline(spec, g, cols, iters_per_solve, p):
+    """The oracle (FP64, numpy) on a bounded sample: FS-QRPPA steps on the first
+    `cols` columns at the full n, scaled by p / cols to the whole design."""
+    import numpy as np
+    from datagen import native
+    from oracle import pqr
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # noqa: BLE001
+        threads = len(os.sched_getaffinity(0))
+    X = native.genotype_host(spec.n, cols, g["thr"][:cols], spec.seed, spec.tag)
+    Xt, _, _ = pqr.standardize(X.astype(np.float64))
+    X1 = pqr.with_intercept(Xt)
+    del X, Xt
+    y = g["y"]
+    G = max(1, cols // 2000)
+    blocks = pqr.partition(cols, G, align=16, intercept_block=True)
+    mu = pqr.default_mu(y, G + 1, 0.1)
+    eta = np.array([1.01 * mu * (spec.n if len(b) == 1 else (np.sqrt(spec.n) + np.sqrt(len(b))) ** 2)
+                    for b in blocks])
+    lam = np.full(cols + 1, 0.1 * pqr.lambda_max(X1, y, 0.5))
+    lam[0] = 0.0
+    beta, z, theta = pqr.zero_start(y, cols + 1)
+    t0 = time.perf_counter()
+    k = 0
+    while True:
+        beta, z, theta = pqr.fsqrppa_step(X1, y, 0.5, lam, blocks, mu, eta, beta, z, theta)
+        k += 1
+        el = time.perf_counter() - t0
+        if (k >= 3 and el > 10.0) or k >= 50:
+            break
+    per_iter_full = (el / k) * (p / cols)
+    sec_per_solve = per_iter_full * iters_per_solve
+    return dict(value=1.0 / sec_per_solve, unit="solves/s", cores=threads, kind="oracle",
+                sample=(f"{k} FS-QRPPA iterations of the FP64 oracle on the first {cols} of "
+                        f"{p} columns (n={spec.n}, {el:.1f} s), per-iteration time scaled by "
+                        f"p/{cols} and multiplied by the GPU's mean iterations per solve "
+                        f"({iters_per_solve:.0f})"),
+                sec_per_iteration_full=per_iter_full)
+
+
+def main():
+    a = parse()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_2601_02826_amd as pq
+
+    t0 = time.perf_counter()
+    spec, g, Xc = make_workload(a.n, a.p)
+    log(f"workload generated in {time.perf_counter() - t0:.1f}s")
+    t0 = time.perf_counter()
+    ctx = pq.Context.from_tensor(Xc, store_fmt=a.fmt, standardize=True, G=a.G, tol_gap=a.tol,
+                                 cert_every=a.cert_every, max_iter=a.max_iter, profile=1)
+    ctx._keep = None
+    del Xc
+    torch.cuda.empty_cache()
+    setup_s = time.perf_counter() - t0
+    log(f"setup (encode, column statistics, Lanczos step sizes) {setup_s:.2f}s")
+    y = g["y"]
+    lmax = ctx.lambda_max(y, 0.5)
+    lams = lmax * 0.01 ** (np.arange(a.npath) / 19.0)
+    if a.calibrate_copy > 0:
+        src = torch.ones(a.calibrate_copy << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    for w in range(a.warmup):
+        run_path(ctx, y, lams)
+        log(f"warmup step {w + 1}/{a.warmup} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps = []
+    for k in range(a.steps):
+        recs = run_path(ctx, y, lams)
+        steps.append(recs)
+        log(f"step {k + 1}/{a.steps}: iters " + " ".join(str(r["iters"]) for r in recs))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    recs = [r for s in steps for r in s]
+    solves = len(recs)
+    iters = sum(r["iters"] for r in recs)
+    passes = sum(r["x_passes"] for r in recs)
+    sweep_ms = sum(r["sweep_ms"] for r in recs)
+    launches = sum(r["sweep_launches"] for r in recs)
+    conv = sum(r["status"] == 0 for r in recs)
+    sweep_avg_ms = sweep_ms / max(1, launches)
+    n, p = a.n, a.p
+    alg_bytes = n * p * BYTES_PER[a.fmt] + 4 * n + 20 * p
+    achieved = alg_bytes / (sweep_avg_ms * 1e-3) / 1e9
+    per_solve = elapsed / solves
+
+    cpu = None
+    if a.cpu_cols > 0:
+        try:
+            cpu = cpu_baseline(spec, g, a.cpu_cols, iters / solves, p)
+        except Exception as e:  # noqa: BLE001
+            log(f"cpu baseline failed: {e}")
+    out = {
+        "metric": METRIC,
+        "value": solves / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": elapsed / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"genotype lambda path, n={n} p={p} X {a.fmt}, tau=0.5, "
+                               f"{a.npath} lambdas lambda_max..0.01 lambda_max, warm starts, "
+                               f"certified rel. duality gap <= {a.tol:g}",
+                   "n": n, "p": p, "x_format": a.fmt, "tau": 0.5, "path_points": a.npath,
+                   "tol_gap": a.tol, "blocks": a.G, "parallelism": "single GPU"},
+        "time_to_kkt_s_per_solve": per_solve,
+        "solves_converged": f"{conv}/{solves}",
+        "iterations_per_solve": iters / solves,
+        "x_passes_per_s": passes / elapsed,
+        "setup_s": setup_s,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic_from_profile(a.fmt, n, p),
+                     "kernel": "k_sweep (X~^T theta + weighted soft threshold)",
+                     "kernel_avg_ms": sweep_avg_ms, "launches": launches,
+                     "algorithmic_bytes_per_launch": alg_bytes},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -85,6 +85,11 @@ typedef struct {
   int cert_every;       /* iterations between FP64 certificates; default 50     */
   int64_t max_iter;     /* default 1e6                                         */
   void* stream;         /* hipStream_t; NULL = default stream                  */
+  int profile;          /* 1 = time every sweep launch with HIP events on `stream` */
+  int intercept_block;  /* 1 (default) = the intercept is a block of its own (p_1 = 1,
+                           Lambda = n) and the G feature blocks follow; 0 = the
+                           intercept is the first column of the first feature block.
+                           Set through pqr_default_options; 0 is honoured as given. */
 } pqr_options;
 
 typedef struct pqr_ctx pqr_ctx;
@@ -109,6 +114,8 @@ typedef struct {
   double lambda_max;    /* smallest lambda with the null fit optimal (same tau, weights) */
   double mu;            /* the mu used                                          */
   double seconds;       /* wall time of the call                                */
+  double sweep_ms;      /* with opt.profile: summed duration of the sweep kernels  */
+  int64_t sweep_launches;
 } pqr_result;
 
 typedef enum {
@@ -155,8 +162,12 @@ pqr_status pqr_kkt(pqr_ctx* ctx, const double* y, double tau, double lambda,
 pqr_status pqr_lambda_max(pqr_ctx* ctx, const double* y, double tau, const double* weights,
                           double* lambda_max, double* score);
 
-/* Blocks and step sizes in use: bounds (host, G+1 ints, feature-column
- * boundaries, block 0 also holds the intercept), Lambda (host, G doubles). */
+/* Blocks in use.  *G receives the total number of blocks B (the G of
+ * eq. fsppa_update, intercept block included when it is separate).  bounds
+ * (host, B+1 ints) are feature-column boundaries: block b holds the feature
+ * columns [bounds[b], bounds[b+1]); block 0 also holds the intercept (with
+ * intercept_block = 1 it holds only the intercept: bounds[0] = bounds[1] = 0).
+ * Lambda (host, B doubles) are the estimates of Lambda_max(X~_b^T X~_b). */
 pqr_status pqr_blocks(pqr_ctx* ctx, int* G, int* bounds, double* Lambda);
 
 /* One or more iterations from a given state with every parameter explicit,

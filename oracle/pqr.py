@@ -70,18 +70,21 @@ def z_prox(z, theta, tau, n, mu):
 # Partition and step sizes (decomposition of X; M_g = eta_g I, eta_g > mu Lambda_max)
 # ----------------------------------------------------------------------------
 
-def partition(p, G, align=1):
-    """Contiguous near-equal blocks over the p feature columns; block 0 also holds
-    the intercept.  Feature boundaries b_g = align * floor(g * ceil(p/align) / G),
-    b_G = p.  Returns a list of index arrays over the full columns 0..p."""
+def partition(p, G, align=1, intercept_block=False):
+    """Contiguous near-equal blocks over the p feature columns (the decomposition
+    of X into X_1..X_G; the paper fixes only sum p_g = p + 1).  Feature boundaries
+    b_g = align * floor(g * ceil(p/align) / G), b_G = p.  The intercept (column 0)
+    is either the first column of the first block, or, with intercept_block, a
+    block of its own placed first (G + 1 blocks in all).  Returns a list of index
+    arrays over the full columns 0..p."""
     units = -(-p // align)
     if not 1 <= G <= units:
         raise ValueError("need 1 <= G <= ceil(p / align)")
     b = [min(p, align * ((g * units) // G)) for g in range(G)] + [p]
-    blocks = []
+    blocks = [np.array([0])] if intercept_block else []
     for g in range(G):
         cols = np.arange(1 + b[g], 1 + b[g + 1])
-        if g == 0:
+        if g == 0 and not intercept_block:
             cols = np.concatenate([[0], cols])
         blocks.append(cols)
     return blocks

@@ -32,7 +32,8 @@ class pqr_options(ctypes.Structure):
                 ("eta_margin", ctypes.c_double), ("lanczos_steps", ctypes.c_int),
                 ("iter_prec", ctypes.c_int), ("tol_gap", ctypes.c_double),
                 ("cert_every", ctypes.c_int), ("max_iter", ctypes.c_int64),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("profile", ctypes.c_int),
+                ("intercept_block", ctypes.c_int)]
 
 
 class pqr_result(ctypes.Structure):
@@ -41,7 +42,8 @@ class pqr_result(ctypes.Structure):
                 ("certs", ctypes.c_int64), ("nnz", ctypes.c_int64),
                 ("primal", ctypes.c_double), ("dual", ctypes.c_double),
                 ("rel_gap", ctypes.c_double), ("lambda_max", ctypes.c_double),
-                ("mu", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("mu", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("sweep_ms", ctypes.c_double), ("sweep_launches", ctypes.c_int64)]
 
 
 SYMBOLS = ["pqr_default_options", "pqr_create", "pqr_solve", "pqr_kkt", "pqr_lambda_max",
@@ -202,7 +204,8 @@ class Context:
         return Result(beta=beta, beta_std=beta_std, z=z, theta=theta, iters=out.iters,
                       x_passes=out.x_passes, certs=out.certs, nnz=out.nnz, primal=out.primal,
                       dual=out.dual, rel_gap=out.rel_gap, lambda_max=out.lambda_max, mu=out.mu,
-                      seconds=out.seconds, status=st)
+                      seconds=out.seconds, sweep_ms=out.sweep_ms,
+                      sweep_launches=out.sweep_launches, status=st)
 
     def kkt(self, y, tau, lam, beta_std, theta, weights=None):
         rep = np.zeros(4)

@@ -264,9 +264,12 @@ __global__ __launch_bounds__(256) void k_init_r(IterBufs<T> b, IterParams ip, in
 
 // ---------------------------------------------------------------------------
 template <int FMT, int RPL, typename T>
-static void launch_fmt(const Geom& g, const IterBufs<T>& b, const IterParams& ip, hipStream_t s) {
+static void launch_fmt(const Geom& g, const IterBufs<T>& b, const IterParams& ip, hipStream_t s,
+                       hipEvent_t ev0, hipEvent_t ev1) {
   const int64_t ng = g.ngroups();
+  if (ev0) (void)hipEventRecord(ev0, s);
   hipLaunchKernelGGL((k_sweep<FMT, RPL, T>), dim3((unsigned)((ng + 3) / 4)), dim3(256), 0, s, g, b);
+  if (ev1) (void)hipEventRecord(ev1, s);
   hipLaunchKernelGGL((k_compact<T>), dim3(1), dim3(1024), 0, s, ng, b, ip.eta0, 1);
   hipLaunchKernelGGL((k_axpy<FMT, RPL, T>), dim3((unsigned)((g.nchunks() + 3) / 4), ip.smax),
                      dim3(256), 0, s, g, b, ip.smax, ip.min_per);
@@ -303,8 +306,8 @@ static void prepare_fmt(const Geom& g, const IterBufs<T>& b, const IterParams& i
 
 template <typename T>
 hipError_t launch_iteration(const Geom& g, const IterBufs<T>& b, const IterParams& ip,
-                            hipStream_t s) {
-  PQR_DISPATCH(launch_fmt, g, b, ip, s)
+                            hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  PQR_DISPATCH(launch_fmt, g, b, ip, s, ev0, ev1)
   return hipGetLastError();
 }
 
@@ -315,8 +318,8 @@ hipError_t launch_prepare_state(const Geom& g, const IterBufs<T>& b, const IterP
   return hipGetLastError();
 }
 
-template hipError_t launch_iteration<float>(const Geom&, const IterBufs<float>&, const IterParams&, hipStream_t);
-template hipError_t launch_iteration<double>(const Geom&, const IterBufs<double>&, const IterParams&, hipStream_t);
+template hipError_t launch_iteration<float>(const Geom&, const IterBufs<float>&, const IterParams&, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_iteration<double>(const Geom&, const IterBufs<double>&, const IterParams&, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_prepare_state<float>(const Geom&, const IterBufs<float>&, const IterParams&, hipStream_t);
 template hipError_t launch_prepare_state<double>(const Geom&, const IterBufs<double>&, const IterParams&, hipStream_t);
 

@@ -283,7 +283,8 @@ hipError_t launch_lanczos_init(int64_t n, int64_t n_pad, int G, float* q, float*
 // w = K_g q: sum of the block's partials (+ the intercept term for block 0);
 // alpha_k = q.w; w -= alpha_k q + beta_{k-1} q_prev; beta_k = |w|; q <- w / beta_k.
 __global__ __launch_bounds__(1024) void k_lanczos_step(int64_t n, int64_t n_pad, int splits, int k,
-                                                       int T, const float* __restrict__ partial,
+                                                       int T, int icpt_in_block0,
+                                                       const float* __restrict__ partial,
                                                        float* q, float* qprev, float* wbuf,
                                                        float* qsum, double* alpha, double* beta) {
   __shared__ double red[2 * 16];
@@ -291,7 +292,7 @@ __global__ __launch_bounds__(1024) void k_lanczos_step(int64_t n, int64_t n_pad,
   float* qb = q + (int64_t)blk * n_pad;
   float* pb = qprev + (int64_t)blk * n_pad;
   float* wb = wbuf + (int64_t)blk * n_pad;
-  const double u0 = blk == 0 ? (double)qsum[0] : 0.0;
+  const double u0 = (blk == 0 && icpt_in_block0) ? (double)qsum[0] : 0.0;
   const double bprev = k > 0 ? beta[blk * T + k - 1] : 0.0;
   double s[2] = {0, 0};
   for (int64_t i = threadIdx.x; i < n; i += 1024) {
@@ -327,10 +328,11 @@ __global__ __launch_bounds__(1024) void k_lanczos_step(int64_t n, int64_t n_pad,
 }
 
 hipError_t launch_lanczos_step(int64_t n, int64_t n_pad, int G, int splits, int k, int T,
-                               const float* partial, float* q, float* qprev, float* wbuf,
-                               float* qsum, double* alpha, double* beta, hipStream_t s) {
-  hipLaunchKernelGGL(k_lanczos_step, dim3(G), dim3(1024), 0, s, n, n_pad, splits, k, T, partial, q,
-                     qprev, wbuf, qsum, alpha, beta);
+                               int icpt_in_block0, const float* partial, float* q, float* qprev,
+                               float* wbuf, float* qsum, double* alpha, double* beta,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_lanczos_step, dim3(G), dim3(1024), 0, s, n, n_pad, splits, k, T,
+                     icpt_in_block0, partial, q, qprev, wbuf, qsum, alpha, beta);
   return hipGetLastError();
 }
 

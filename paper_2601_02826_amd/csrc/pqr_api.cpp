@@ -21,10 +21,13 @@ struct pqr_ctx {
   int standardize = 1;
   pqr_options opt{};
   hipStream_t s = nullptr;
-  int G = 0;
-  std::vector<int> bounds;      // feature-column boundaries of the blocks (G+1)
-  std::vector<int> gbound;      // group boundaries of the blocks (G+1)
-  std::vector<double> Lambda;   // Lambda_max(X~_g^T X~_g) estimates
+  int G = 0;                    // total blocks (intercept block included when separate)
+  int Gf = 0;                   // feature blocks
+  int icpt_own = 1;             // intercept forms block 0 on its own
+  std::vector<int> bounds;      // feature-column boundaries of the G blocks (G+1)
+  std::vector<int> gbound;      // group boundaries of the Gf feature blocks (Gf+1)
+  std::vector<int> gblock_h;    // block of every column group
+  std::vector<double> Lambda;   // Lambda_max(X~_b^T X~_b) estimates (G)
   int smax = 256, min_per = 4;
 
   // design and column parameters
@@ -46,12 +49,14 @@ struct pqr_ctx {
   double *y_d = nullptr, *theta_p = nullptr, *beta_d = nullptr, *clam_d = nullptr, *v_d = nullptr,
          *gpart = nullptr, *partial64 = nullptr, *bpart64 = nullptr, *out_d = nullptr,
          *scratch64 = nullptr, *bt_out = nullptr;
+  void* beta_best = nullptr;     // coefficients of the best primal iterate seen (iterate type)
   int64_t bpart64_len = 0;
   double* out_h = nullptr;   // pinned
 
   bool have_state = false;
   double state_mu = 0.0;
   std::vector<void*> allocs;
+  std::vector<hipEvent_t> events;   // 2 per iteration of a chunk when profiling
 };
 
 namespace {
@@ -176,6 +181,8 @@ extern "C" void pqr_default_options(pqr_options* o) {
   o->cert_every = 50;
   o->max_iter = 1000000;
   o->stream = nullptr;
+  o->profile = 0;
+  o->intercept_block = 1;
 }
 
 extern "C" const char* pqr_status_string(pqr_status s) {
@@ -198,6 +205,7 @@ extern "C" void pqr_destroy(pqr_ctx* ctx) {
   if (ctx->s) (void)hipStreamSynchronize(ctx->s);
   else (void)hipDeviceSynchronize();
   for (void* p : ctx->allocs) (void)hipFree(p);
+  for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
   if (ctx->out_h) (void)hipHostFree(ctx->out_h);
   delete ctx;
 }
@@ -236,64 +244,76 @@ static pqr_status create_impl(pqr_ctx* ctx, const pqr_design* X) {
   HIPCHK(launch_colparams(sum, sumsq, n, p, g.p_pad, ctx->standardize, ctx->cm_d, ctx->cinv_d,
                           ctx->sd_d, ctx->cm_f, ctx->cinv_f, s));
 
-  // blocks: contiguous near-equal runs of 16-column groups, intercept in block 0
-  int G = ctx->opt.G > 0 ? ctx->opt.G : 48;
-  if (G > ng) G = (int)ng;
+  // blocks: contiguous near-equal runs of 16-column groups; the intercept is
+  // either a block of its own (block 0) or the first column of block 0
+  int Gf = ctx->opt.G > 0 ? ctx->opt.G : 48;
+  if (Gf > ng) Gf = (int)ng;
+  ctx->Gf = Gf;
+  ctx->icpt_own = ctx->opt.intercept_block ? 1 : 0;
+  const int off = ctx->icpt_own;
+  const int G = Gf + off;
   ctx->G = G;
-  ctx->gbound.resize(G + 1);
-  ctx->bounds.resize(G + 1);
-  for (int b = 0; b < G; ++b) ctx->gbound[b] = (int)(((int64_t)b * ng) / G);
-  ctx->gbound[G] = (int)ng;
-  for (int b = 0; b <= G; ++b)
-    ctx->bounds[b] = (int)std::min<int64_t>(p, (int64_t)kGroup * ctx->gbound[b]);
+  ctx->gbound.resize(Gf + 1);
+  for (int b = 0; b < Gf; ++b) ctx->gbound[b] = (int)(((int64_t)b * ng) / Gf);
+  ctx->gbound[Gf] = (int)ng;
+  ctx->bounds.assign(G + 1, 0);
+  for (int b = 0; b <= Gf; ++b)
+    ctx->bounds[b + off] = (int)std::min<int64_t>(p, (int64_t)kGroup * ctx->gbound[b]);
   ctx->bounds[G] = (int)p;
-  std::vector<int> gblock(ng);
-  for (int b = 0; b < G; ++b)
-    for (int q = ctx->gbound[b]; q < ctx->gbound[b + 1]; ++q) gblock[q] = b;
+  std::vector<int> fblock(ng);   // feature block of every group (for Lanczos)
+  ctx->gblock_h.resize(ng);
+  for (int b = 0; b < Gf; ++b)
+    for (int q = ctx->gbound[b]; q < ctx->gbound[b + 1]; ++q) {
+      fblock[q] = b;
+      ctx->gblock_h[q] = b + off;
+    }
   int *gblock_d, *bstart_d;
   TRY(dalloc(ctx, &gblock_d, ng * 4));
-  TRY(dalloc(ctx, &bstart_d, (G + 1) * 4));
-  HIPCHK(hipMemcpyAsync(gblock_d, gblock.data(), ng * 4, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(bstart_d, ctx->gbound.data(), (G + 1) * 4, hipMemcpyHostToDevice, s));
+  TRY(dalloc(ctx, &bstart_d, (Gf + 1) * 4));
+  HIPCHK(hipMemcpyAsync(gblock_d, fblock.data(), ng * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(bstart_d, ctx->gbound.data(), (Gf + 1) * 4, hipMemcpyHostToDevice, s));
   std::vector<int> iota(ng);
   for (int64_t q = 0; q < ng; ++q) iota[q] = (int)q;
   TRY(dalloc(ctx, &ctx->iota, ng * 4));
   HIPCHK(hipMemcpyAsync(ctx->iota, iota.data(), ng * 4, hipMemcpyHostToDevice, s));
 
-  // Lanczos estimates of Lambda_max(X~_g^T X~_g), all blocks together
+  // Lanczos estimates of Lambda_max(X~_b^T X~_b), all feature blocks together
   const int T = std::max(2, ctx->opt.lanczos_steps > 0 ? ctx->opt.lanczos_steps : 40);
   const int splits = 8;
   float *q, *qprev, *wbuf, *qsum, *u, *lpart;
   double *al, *be;
-  TRY(dalloc(ctx, &q, (size_t)G * g.n_pad * 4));
-  TRY(dalloc(ctx, &qprev, (size_t)G * g.n_pad * 4));
-  TRY(dalloc(ctx, &wbuf, (size_t)G * g.n_pad * 4));
-  TRY(dalloc(ctx, &qsum, G * 4));
+  TRY(dalloc(ctx, &q, (size_t)Gf * g.n_pad * 4));
+  TRY(dalloc(ctx, &qprev, (size_t)Gf * g.n_pad * 4));
+  TRY(dalloc(ctx, &wbuf, (size_t)Gf * g.n_pad * 4));
+  TRY(dalloc(ctx, &qsum, Gf * 4));
   TRY(dalloc(ctx, &u, g.p_pad * 4));
-  TRY(dalloc(ctx, &lpart, (size_t)G * splits * g.n_pad * 4));
-  TRY(dalloc(ctx, &al, (size_t)G * T * 8));
-  TRY(dalloc(ctx, &be, (size_t)G * T * 8));
-  HIPCHK(launch_lanczos_init(n, g.n_pad, G, q, qprev, qsum, s));
+  TRY(dalloc(ctx, &lpart, (size_t)Gf * splits * g.n_pad * 4));
+  TRY(dalloc(ctx, &al, (size_t)Gf * T * 8));
+  TRY(dalloc(ctx, &be, (size_t)Gf * T * 8));
+  HIPCHK(launch_lanczos_init(n, g.n_pad, Gf, q, qprev, qsum, s));
   for (int k = 0; k < T; ++k) {
     HIPCHK(launch_block_dots(g, q, g.n_pad, gblock_d, ctx->cm_f, ctx->cinv_f, qsum, u, s));
-    HIPCHK(launch_block_axpy(g, u, ctx->cm_f, ctx->cinv_f, bstart_d, G, splits, lpart, s));
-    HIPCHK(launch_lanczos_step(n, g.n_pad, G, splits, k, T, lpart, q, qprev, wbuf, qsum, al, be, s));
+    HIPCHK(launch_block_axpy(g, u, ctx->cm_f, ctx->cinv_f, bstart_d, Gf, splits, lpart, s));
+    HIPCHK(launch_lanczos_step(n, g.n_pad, Gf, splits, k, T, ctx->icpt_own ? 0 : 1, lpart, q,
+                               qprev, wbuf, qsum, al, be, s));
   }
-  std::vector<double> ha((size_t)G * T), hb((size_t)G * T);
+  std::vector<double> ha((size_t)Gf * T), hb((size_t)Gf * T);
   HIPCHK(hipMemcpyAsync(ha.data(), al, ha.size() * 8, hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(hb.data(), be, hb.size() * 8, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  ctx->Lambda.resize(G);
-  for (int b = 0; b < G; ++b) {
+  ctx->Lambda.assign(G, 0.0);
+  if (off) ctx->Lambda[0] = (double)n;   // the intercept column alone: 1^T 1 = n
+  for (int b = 0; b < Gf; ++b) {
     int k = T;
     for (int i = 0; i < T; ++i)
       if (hb[(size_t)b * T + i] < 1e-12 * std::max(1.0, std::fabs(ha[(size_t)b * T]))) { k = i + 1; break; }
-    ctx->Lambda[b] = std::max(ritz_upper(&ha[(size_t)b * T], &hb[(size_t)b * T], k), 1e-30);
+    ctx->Lambda[b + off] = std::max(ritz_upper(&ha[(size_t)b * T], &hb[(size_t)b * T], k), 1e-30);
   }
 
   // iteration buffers
   const size_t ts = tsize(ctx);
   TRY(dalloc(ctx, &ctx->beta, g.p_pad * ts));
+  TRY(dalloc(ctx, &ctx->beta_best, g.p_pad * ts));
   TRY(dalloc(ctx, &ctx->clam_t, g.p_pad * ts));
   TRY(dalloc(ctx, &ctx->cm_t, g.p_pad * ts));
   TRY(dalloc(ctx, &ctx->cinv_t, g.p_pad * ts));
@@ -447,8 +467,7 @@ pqr_status set_eta(pqr_ctx* ctx, double mu, const double* eta_explicit, double e
     eta[b] = eta_explicit ? eta_explicit[b]
                           : eta_scale * (1.0 + ctx->opt.eta_margin) * mu * ctx->Lambda[b];
   std::vector<T> ge(g.ngroups());
-  for (int b = 0; b < ctx->G; ++b)
-    for (int q = ctx->gbound[b]; q < ctx->gbound[b + 1]; ++q) ge[q] = (T)eta[b];
+  for (int64_t q = 0; q < g.ngroups(); ++q) ge[q] = (T)eta[ctx->gblock_h[q]];
   HIPCHK(hipMemcpyAsync(ctx->geta_t, ge.data(), ge.size() * sizeof(T), hipMemcpyHostToDevice, ctx->s));
   HIPCHK(hipStreamSynchronize(ctx->s));
   ip.tau = tau;
@@ -544,13 +563,16 @@ pqr_status certificate(pqr_ctx* ctx, double tau, Cert* out) {
   return PQR_OK;
 }
 
+// Copies the coefficients `bsrc` (intercept beta0) and the current z, theta out.
 template <typename T>
-pqr_status export_state(pqr_ctx* ctx, pqr_result* res) {
+pqr_status export_state(pqr_ctx* ctx, pqr_result* res, const void* bsrc, double beta0) {
   const Geom& g = ctx->g;
   hipStream_t s = ctx->s;
   Ctl c;
   HIPCHK(hipMemcpyAsync(&c, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-  HIPCHK(launch_to_double<T>((const T*)ctx->beta, g.p_pad, ctx->beta_d, s));
+  HIPCHK(hipStreamSynchronize(s));
+  c.beta0 = beta0;
+  HIPCHK(launch_to_double<T>((const T*)bsrc, g.p_pad, ctx->beta_d, s));
   std::vector<double> b(g.p);
   HIPCHK(hipMemcpyAsync(b.data(), ctx->beta_d, g.p * 8, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -624,20 +646,57 @@ pqr_status solve_impl(pqr_ctx* ctx, const double* y, double tau, double lambda,
 
   const Geom& g = ctx->g;
   hipStream_t s = ctx->s;
-  int64_t it = 0, certs = 0, restarts = 0;
+  int64_t it = 0, certs = 0, restarts = 0, sweeps = 0;
+  double sweep_ms = 0.0;
+  // Any iterate's P(beta) bounds P* from above and any feasible dual point's
+  // value bounds it from below, so the gap certified so far is
+  // min primal - max dual; the coefficients reported are the best primal ones.
+  double best_primal = INFINITY, best_dual = -INFINITY, best_beta0 = 0.0;
+  auto track = [&](const Cert& c) -> pqr_status {
+    best_dual = std::max(best_dual, c.dual);
+    if (c.primal < best_primal) {
+      best_primal = c.primal;
+      Ctl cc;
+      HIPCHK(hipMemcpyAsync(&cc, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(ctx->beta_best, ctx->beta, g.p_pad * sizeof(T),
+                            hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipStreamSynchronize(s));
+      best_beta0 = cc.beta0;
+    }
+    return PQR_OK;
+  };
+  auto best_gap = [&]() {
+    return (best_primal - best_dual) / std::max(std::fabs(best_primal), 1e-300);
+  };
+  if (ctx->opt.profile && ctx->events.empty()) {
+    ctx->events.resize(2 * (size_t)ctx->opt.cert_every);
+    for (auto& e : ctx->events) HIPCHK(hipEventCreate(&e));
+  }
   Cert cert{};
   pqr_status status = PQR_ERR_NOT_CONVERGED;
   TRY(certificate<T>(ctx, tau, &cert));
   ++certs;
-  if (cert.rel_gap <= ctx->opt.tol_gap) status = PQR_OK;
+  TRY(track(cert));
+  if (best_gap() <= ctx->opt.tol_gap) status = PQR_OK;
   while (status != PQR_OK && it < ctx->opt.max_iter) {
     const int64_t chunk = std::min<int64_t>(ctx->opt.cert_every, ctx->opt.max_iter - it);
     const IterBufs<T> b = bufs<T>(ctx);
-    for (int64_t k = 0; k < chunk; ++k) HIPCHK(launch_iteration<T>(g, b, ip, s));
+    const bool prof = ctx->opt.profile != 0;
+    for (int64_t k = 0; k < chunk; ++k)
+      HIPCHK(launch_iteration<T>(g, b, ip, s, prof ? ctx->events[2 * k] : nullptr,
+                                 prof ? ctx->events[2 * k + 1] : nullptr));
     it += chunk;
     Ctl c;
     HIPCHK(hipMemcpyAsync(&c, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    if (prof) {
+      for (int64_t k = 0; k < chunk; ++k) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ctx->events[2 * k], ctx->events[2 * k + 1]));
+        sweep_ms += ms;
+      }
+      sweeps += chunk;
+    }
     if (!std::isfinite(c.delta) || c.n_increase > 25) {
       // the H-norm successive difference grows: the metric is not positive
       // definite (eta_g below mu Lambda_max); double eta and restart
@@ -653,10 +712,15 @@ pqr_status solve_impl(pqr_ctx* ctx, const double* y, double tau, double lambda,
     }
     TRY(certificate<T>(ctx, tau, &cert));
     ++certs;
-    if (cert.rel_gap <= ctx->opt.tol_gap) status = PQR_OK;
+    TRY(track(cert));
+    if (best_gap() <= ctx->opt.tol_gap) status = PQR_OK;
   }
+  cert.primal = best_primal;
+  cert.dual = best_dual;
+  cert.gap = best_primal - best_dual;
+  cert.rel_gap = best_gap();
   if (out) {
-    TRY(export_state<T>(ctx, out));
+    TRY(export_state<T>(ctx, out, ctx->beta_best, best_beta0));
     out->iters = it;
     out->certs = certs;
     out->x_passes = it + certs + 1;
@@ -666,6 +730,8 @@ pqr_status solve_impl(pqr_ctx* ctx, const double* y, double tau, double lambda,
     out->lambda_max = lmax;
     out->mu = mu;
     out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    out->sweep_ms = sweep_ms;
+    out->sweep_launches = sweeps;
   }
   if (status == PQR_ERR_NOT_CONVERGED)
     ctx->err = "max_iter reached with relative gap " + std::to_string(cert.rel_gap);
@@ -715,7 +781,10 @@ pqr_status iterate_impl(pqr_ctx* ctx, const double* y, double tau, double lambda
   r.beta_std = beta_std;
   r.z = z;
   r.theta = theta;
-  return export_state<T>(ctx, &r);
+  Ctl c;
+  HIPCHK(hipMemcpyAsync(&c, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->s));
+  HIPCHK(hipStreamSynchronize(ctx->s));
+  return export_state<T>(ctx, &r, ctx->beta, c.beta0);
 }
 }  // namespace
 

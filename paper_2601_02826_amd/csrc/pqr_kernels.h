@@ -44,10 +44,11 @@ struct IterParams {
   int smax, min_per;
 };
 
-// One FS-QRPPA iteration = sweep, compact, axpy, update.
+// One FS-QRPPA iteration = sweep, compact, axpy, update.  With non-null
+// events, ev0/ev1 are recorded around the sweep kernel.
 template <typename T>
 hipError_t launch_iteration(const Geom& g, const IterBufs<T>& b, const IterParams& ip,
-                            hipStream_t s);
+                            hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // Recompute the cached residual r = X~beta + beta0 + z - y and sum(theta) for a
 // given state (after a warm start); also rebuilds the active list.
@@ -109,8 +110,9 @@ hipError_t launch_block_dots(const Geom& g, const float* q, int64_t qstride, con
 hipError_t launch_block_axpy(const Geom& g, const float* u, const float* cm, const float* cinv,
                              const int* bstart, int G, int splits, float* partial, hipStream_t s);
 hipError_t launch_lanczos_step(int64_t n, int64_t n_pad, int G, int splits, int k, int T,
-                               const float* partial, float* q, float* qprev, float* wbuf,
-                               float* qsum, double* alpha, double* beta, hipStream_t s);
+                               int icpt_in_block0, const float* partial, float* q, float* qprev,
+                               float* wbuf, float* qsum, double* alpha, double* beta,
+                               hipStream_t s);
 hipError_t launch_lanczos_init(int64_t n, int64_t n_pad, int G, float* q, float* qprev,
                                float* qsum, hipStream_t s);
 

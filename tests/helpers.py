@@ -33,8 +33,8 @@ def oracle_design(X, standardize):
     return pqr.with_intercept(Xf), None, None
 
 
-def oracle_blocks(p, G):
-    return pqr.partition(p, G, align=16)
+def oracle_blocks(p, G, intercept_block=True):
+    return pqr.partition(p, G, align=16, intercept_block=intercept_block)
 
 
 def lam_vector(p, lam, weights=None):

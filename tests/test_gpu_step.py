@@ -23,20 +23,24 @@ def _check(got, want, rtol, label):
         assert err <= rtol, f"{label}: {name} rel err {err:.3e} > {rtol:.1e}"
 
 
+@pytest.mark.parametrize("icpt", [True, False])
 @pytest.mark.parametrize("iter_prec,rtol", [("f64", 1e-11), ("f32", 2e-5)])
 @pytest.mark.parametrize("n,p,G", [(300, 517, 5), (1100, 130, 3)])
-def test_step_parity_gaussian(iter_prec, rtol, n, p, G):
+def test_step_parity_gaussian(iter_prec, rtol, n, p, G, icpt):
     import paper_2601_02826_amd as pq
     X, y = H.gaussian_problem(n, p, seed=21)
     X1, _, _ = H.oracle_design(X, False)
     tau = 0.3
     lam = 0.2 * pqr.lambda_max(X1, y, tau)
     ctx = pq.Context.from_tensor(H.to_device_cols(X), store_fmt="f64", standardize=False, G=G,
-                                 iter_prec=iter_prec)
+                                 iter_prec=iter_prec, intercept_block=int(icpt))
     Gg, bounds, Lam = ctx.blocks()
-    blocks = H.oracle_blocks(p, G)
-    assert Gg == G
+    blocks = H.oracle_blocks(p, G, icpt)
+    assert Gg == len(blocks)
     assert [int(b[-1]) for b in blocks] == [int(v) for v in bounds[1:]]
+    # the Lanczos estimates bound the exact block spectra from above, within the margin
+    exact = np.array([pqr.block_lambda_max(X1[:, b]) for b in blocks])
+    assert np.all(Lam >= exact * (1 - 1e-6)) and np.all(Lam <= exact * 1.05)
     mu = pqr.default_mu(y, G, 0.1)
     eta = pqr.step_sizes(X1, blocks, mu)
     lam_vec = H.lam_vector(p, lam)
