@@ -88,16 +88,16 @@ __global__ __launch_bounds__(256) void k_dots64(Geom g, const double* __restrict
   double acc[kGroup];
 #pragma unroll
   for (int c = 0; c < kGroup; ++c) acc[c] = 0;
-  const uint8_t* base = g.X + grp * kGroup * g.ldb;
   const int64_t nch = g.nchunks();
   for (int64_t ch = 0; ch < nch; ++ch) {
     const int64_t row0 = ch * (kWave * RPL) + (int64_t)lane * RPL;
+    const uint8_t* base = g.seg(grp * kGroup, ch);
     double th[RPL];
     load_vec<RPL, double>(tp, row0, th);
 #pragma unroll
     for (int c = 0; c < kGroup; ++c) {
       double x[RPL];
-      load_rows<FMT, RPL, double>(base + c * g.ldb, row0, x);
+      load_rows<FMT, RPL, double>(base + c * g.seg_bytes, (int64_t)lane * RPL, x);
 #pragma unroll
       for (int r = 0; r < RPL; ++r) acc[c] = fma(x[r], th[r], acc[c]);
     }
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256) void k_axpy64(Geom g, CertBufs c, int smax, in
       const double bj = c.beta_d[j] * c.cinv[j];
       if (bj != 0.0) {
         double x[RPL];
-        load_rows<FMT, RPL, double>(g.X + j * g.ldb, row0, x);
+        load_rows<FMT, RPL, double>(g.seg(j, ch), (int64_t)lane * RPL, x);
 #pragma unroll
         for (int r = 0; r < RPL; ++r) acc[r] = fma(x[r], bj, acc[r]);
         off = fma(c.cm[j], bj, off);

@@ -3,9 +3,9 @@
 //   k_sweep    v = X~^T theta for every column (one wavefront per 16-column
 //              group, the design read once) fused with the per-block
 //              weighted soft threshold of eq. beta_update.
-//   k_compact  one workgroup: the ordered list of column groups holding a
-//              nonzero coefficient, the sweep's norm partials, and the
-//              intercept (lambda_0 = 0, so its update is a plain step).
+//   k_count, k_scatter  the ordered list of column groups holding a nonzero
+//              coefficient, the sweep's norm partials, and the intercept
+//              (lambda_0 = 0, so its update is a plain step).
 //   k_axpy     s = X~ beta^{k+1} over the nonzero coefficients only: the
 //              partial products X_g beta_g of the paper, gathered by column
 //              and reduced in a fixed order (no atomics).
@@ -24,18 +24,26 @@ __device__ __forceinline__ void group_dots(const Geom& g, int64_t grp, const T* 
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int c = 0; c < kGroup; ++c) acc[c] = 0;
-  const uint8_t* base = g.X + grp * kGroup * g.ldb;
   const int64_t nch = g.nchunks();
+  const int64_t lrow = (int64_t)lane * RPL;
+  constexpr int B = Batch<FMT, RPL>::value;
   for (int64_t ch = 0; ch < nch; ++ch) {
-    const int64_t row0 = ch * (kWave * RPL) + (int64_t)lane * RPL;
-    T th[RPL];
-    load_vec<RPL, T>(theta, row0, th);
+    const int64_t row0 = ch * (kWave * RPL) + lrow;
+    const uint8_t* base = g.seg(grp * kGroup, ch);
 #pragma unroll
-    for (int c = 0; c < kGroup; ++c) {
-      T x[RPL];
-      load_rows<FMT, RPL, T>(base + c * g.ldb, row0, x);
+    for (int cb = 0; cb < kGroup; cb += B) {
+      Raw<FMT, RPL> raw[B];
 #pragma unroll
-      for (int r = 0; r < RPL; ++r) acc[c] = fma(x[r], th[r], acc[c]);
+      for (int c = 0; c < B; ++c) raw[c] = load_raw<FMT, RPL>(base + (cb + c) * g.seg_bytes, lrow);
+      T th[RPL];
+      load_vec<RPL, T>(theta, row0, th);
+#pragma unroll
+      for (int c = 0; c < B; ++c) {
+        T x[RPL];
+        decode<FMT, RPL, T>(raw[c], x);
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) acc[cb + c] = fma(x[r], th[r], acc[cb + c]);
+      }
     }
   }
 }
@@ -87,35 +95,75 @@ __global__ __launch_bounds__(256) void k_flags(int64_t ngroups, IterBufs<T> b) {
 }
 
 // ---------------------------------------------------------------------------
+// Compaction in two passes over kCompactBlocks contiguous ranges of groups:
+// k_count sums each range's flags and norm partials; k_scatter writes each
+// range's active groups at its offset (ranges in order, groups in order), and
+// its block 0 reduces the norms in a fixed order and steps the intercept.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void compact_range(int64_t ngroups, int64_t& g0, int64_t& g1) {
+  const int64_t per = (ngroups + kCompactBlocks - 1) / kCompactBlocks;
+  g0 = (int64_t)blockIdx.x * per;
+  g1 = g0 + per < ngroups ? g0 + per : ngroups;
+  if (g0 > ngroups) g0 = ngroups;
+}
+
 template <typename T>
-__global__ __launch_bounds__(1024) void k_compact(int64_t ngroups, IterBufs<T> b, double eta0,
-                                                  int step_intercept) {
-  __shared__ int scan[1024];
-  __shared__ double red[4 * 16];
-  const int t = threadIdx.x;
-  const int64_t per = (ngroups + 1023) / 1024;
-  const int64_t g0 = t * per, g1 = g0 + per < ngroups ? g0 + per : ngroups;
-  int cnt = 0;
-  double s[4] = {0, 0, 0, 0};
-  for (int64_t gi = g0; gi < g1; ++gi) {
-    cnt += b.gflag[gi] != 0;
+__global__ __launch_bounds__(1024) void k_count(int64_t ngroups, IterBufs<T> b) {
+  __shared__ double red[5 * 16];
+  int64_t g0, g1;
+  compact_range(ngroups, g0, g1);
+  double s[5] = {0, 0, 0, 0, 0};
+  for (int64_t gi = g0 + threadIdx.x; gi < g1; gi += 1024) {
+    s[4] += b.gflag[gi] != 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) s[k] += (double)b.gnorm[gi * 4 + k];
   }
-  scan[t] = cnt;
+  block_sum<1024, 5, double>(s, red);
+  if (threadIdx.x == 0) {
+    b.bcnt[blockIdx.x] = (int)s[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) b.bnrm[blockIdx.x * 4 + k] = s[k];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_scatter(int64_t ngroups, IterBufs<T> b, double eta0,
+                                                  int step_intercept) {
+  __shared__ int wcnt[16];
+  __shared__ int base_s;
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  int64_t g0, g1;
+  compact_range(ngroups, g0, g1);
+  if (t == 0) {
+    int off = 0;
+    for (int k = 0; k < (int)blockIdx.x; ++k) off += b.bcnt[k];
+    base_s = off;
+  }
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const int v = t >= off ? scan[t - off] : 0;
+  int base = base_s;
+  for (int64_t tile = g0; tile < g1; tile += 1024) {
+    const int64_t gi = tile + t;
+    const bool f = gi < g1 && b.gflag[gi] != 0;
+    const unsigned long long bal = __ballot(f);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wcnt[wid] = __popcll(bal);
     __syncthreads();
-    scan[t] += v;
+    int woff = 0, tot = 0;
+    for (int w = 0; w < 16; ++w) {
+      woff += w < wid ? wcnt[w] : 0;
+      tot += wcnt[w];
+    }
+    if (f) b.list[base + woff + before] = (int)gi;
+    base += tot;
     __syncthreads();
   }
-  int pos = scan[t] - cnt;
-  for (int64_t gi = g0; gi < g1; ++gi)
-    if (b.gflag[gi]) b.list[pos++] = (int)gi;
-  const int total = scan[1023];
-  block_sum<1024, 4, double>(s, red);
-  if (t == 0) {
+  if (blockIdx.x == 0 && t == 0) {
+    double s[4] = {0, 0, 0, 0};
+    int total = 0;
+    for (int k = 0; k < kCompactBlocks; ++k) {
+      total += b.bcnt[k];
+      for (int q = 0; q < 4; ++q) s[q] += b.bnrm[k * 4 + q];
+    }
     Ctl* c = b.ctl;
     double b0 = c->beta0, b0n = b0;
     if (step_intercept) b0n = b0 + c->sum_theta / eta0;   // intercept: lambda_0 = 0
@@ -158,7 +206,7 @@ __global__ __launch_bounds__(256) void k_axpy(Geom g, IterBufs<T> b, int smax, i
       const T bj = b.beta[j] * b.cinv[j];   // coefficient on the raw column
       if (bj != T(0)) {
         T x[RPL];
-        load_rows<FMT, RPL, T>(g.X + j * g.ldb, row0, x);
+        load_rows<FMT, RPL, T>(g.seg(j, ch), (int64_t)lane * RPL, x);
 #pragma unroll
         for (int r = 0; r < RPL; ++r) acc[r] = fma(x[r], bj, acc[r]);
         off = fma(b.cm[j], bj, off);
@@ -270,7 +318,8 @@ static void launch_fmt(const Geom& g, const IterBufs<T>& b, const IterParams& ip
   if (ev0) (void)hipEventRecord(ev0, s);
   hipLaunchKernelGGL((k_sweep<FMT, RPL, T>), dim3((unsigned)((ng + 3) / 4)), dim3(256), 0, s, g, b);
   if (ev1) (void)hipEventRecord(ev1, s);
-  hipLaunchKernelGGL((k_compact<T>), dim3(1), dim3(1024), 0, s, ng, b, ip.eta0, 1);
+  hipLaunchKernelGGL((k_count<T>), dim3(kCompactBlocks), dim3(1024), 0, s, ng, b);
+  hipLaunchKernelGGL((k_scatter<T>), dim3(kCompactBlocks), dim3(1024), 0, s, ng, b, ip.eta0, 1);
   hipLaunchKernelGGL((k_axpy<FMT, RPL, T>), dim3((unsigned)((g.nchunks() + 3) / 4), ip.smax),
                      dim3(256), 0, s, g, b, ip.smax, ip.min_per);
   hipLaunchKernelGGL((k_update<T>), dim3((unsigned)(g.n_pad / 256)), dim3(256), 0, s, b, ip, g.n,
@@ -281,7 +330,8 @@ template <int FMT, int RPL, typename T>
 static void prepare_fmt(const Geom& g, const IterBufs<T>& b, const IterParams& ip, hipStream_t s) {
   const int64_t ng = g.ngroups();
   hipLaunchKernelGGL((k_flags<T>), dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, s, ng, b);
-  hipLaunchKernelGGL((k_compact<T>), dim3(1), dim3(1024), 0, s, ng, b, ip.eta0, 0);
+  hipLaunchKernelGGL((k_count<T>), dim3(kCompactBlocks), dim3(1024), 0, s, ng, b);
+  hipLaunchKernelGGL((k_scatter<T>), dim3(kCompactBlocks), dim3(1024), 0, s, ng, b, ip.eta0, 0);
   hipLaunchKernelGGL((k_axpy<FMT, RPL, T>), dim3((unsigned)((g.nchunks() + 3) / 4), ip.smax),
                      dim3(256), 0, s, g, b, ip.smax, ip.min_per);
   hipLaunchKernelGGL((k_init_r<T>), dim3((unsigned)(g.n_pad / 256)), dim3(256), 0, s, b, ip, g.n,

@@ -29,7 +29,10 @@ __global__ __launch_bounds__(256) void k_encode(const void* __restrict__ src, in
   for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total;
        t += (int64_t)gridDim.x * 256) {
     const int64_t j = t / quads, qd = t - j * quads, i0 = qd * 4;
-    uint8_t* col = dst + j * g.ldb;
+    // point `col` so that col + (bytes of row i0) is row i0's place in its segment
+    const int64_t rows_per_seg = (int64_t)kWave * g.rpl;
+    const int64_t ch = i0 / rows_per_seg;
+    uint8_t* col = dst + (g.seg(j, ch) - g.X) - fmt_col_bytes(g.fmt, ch * rows_per_seg);
     if (g.fmt == F64 && src_fmt == F64) {   // exact copy, no float round trip
       for (int k = 0; k < 4; ++k) {
         const int64_t i = i0 + k;
@@ -98,13 +101,12 @@ __global__ __launch_bounds__(256) void k_colstats(Geom g, double* sum, double* s
   double a[kGroup], b[kGroup];
 #pragma unroll
   for (int c = 0; c < kGroup; ++c) a[c] = b[c] = 0;
-  const uint8_t* base = g.X + grp * kGroup * g.ldb;
   for (int64_t ch = 0; ch < g.nchunks(); ++ch) {
-    const int64_t row0 = ch * (kWave * RPL) + (int64_t)lane * RPL;
+    const uint8_t* base = g.seg(grp * kGroup, ch);
 #pragma unroll
     for (int c = 0; c < kGroup; ++c) {
       double x[RPL];
-      load_rows<FMT, RPL, double>(base + c * g.ldb, row0, x);
+      load_rows<FMT, RPL, double>(base + c * g.seg_bytes, (int64_t)lane * RPL, x);
 #pragma unroll
       for (int r = 0; r < RPL; ++r) { a[c] += x[r]; b[c] = fma(x[r], x[r], b[c]); }
     }
@@ -162,15 +164,15 @@ __global__ __launch_bounds__(256) void k_block_dots(Geom g, const float* __restr
   float acc[kGroup];
 #pragma unroll
   for (int c = 0; c < kGroup; ++c) acc[c] = 0;
-  const uint8_t* base = g.X + grp * kGroup * g.ldb;
   for (int64_t ch = 0; ch < g.nchunks(); ++ch) {
     const int64_t row0 = ch * (kWave * RPL) + (int64_t)lane * RPL;
+    const uint8_t* base = g.seg(grp * kGroup, ch);
     float th[RPL];
     load_vec<RPL, float>(qb, row0, th);
 #pragma unroll
     for (int c = 0; c < kGroup; ++c) {
       float x[RPL];
-      load_rows<FMT, RPL, float>(base + c * g.ldb, row0, x);
+      load_rows<FMT, RPL, float>(base + c * g.seg_bytes, (int64_t)lane * RPL, x);
 #pragma unroll
       for (int r = 0; r < RPL; ++r) acc[c] = fmaf(x[r], th[r], acc[c]);
     }
@@ -207,7 +209,7 @@ __global__ __launch_bounds__(256) void k_block_axpy(Geom g, const float* __restr
       const int64_t j = (int64_t)grp * kGroup + c;
       const float bj = u[j] * cinv[j];
       float x[RPL];
-      load_rows<FMT, RPL, float>(g.X + j * g.ldb, row0, x);
+      load_rows<FMT, RPL, float>(g.seg(j, ch), (int64_t)lane * RPL, x);
 #pragma unroll
       for (int r = 0; r < RPL; ++r) acc[r] = fmaf(x[r], bj, acc[r]);
       off = fmaf(cm[j], bj, off);

@@ -40,8 +40,9 @@ struct pqr_ctx {
   void *beta = nullptr, *clam_t = nullptr, *geta_t = nullptr, *gnorm = nullptr,
        *partial = nullptr, *y_t = nullptr, *z = nullptr, *theta = nullptr, *r = nullptr,
        *cm_t = nullptr, *cinv_t = nullptr;
-  int *gflag = nullptr, *list = nullptr;
+  int *gflag = nullptr, *list = nullptr, *bcnt = nullptr;
   double* bpart = nullptr;
+  double* bnrm = nullptr;
   Ctl* ctl = nullptr;
   Ctl* ctl_kkt = nullptr;
 
@@ -160,6 +161,8 @@ IterBufs<T> bufs(pqr_ctx* ctx) {
   b.theta = (T*)ctx->theta;
   b.r = (T*)ctx->r;
   b.bpart = ctx->bpart;
+  b.bcnt = ctx->bcnt;
+  b.bnrm = ctx->bnrm;
   b.ctl = ctx->ctl;
   return b;
 }
@@ -219,7 +222,7 @@ static pqr_status create_impl(pqr_ctx* ctx, const pqr_design* X) {
   g.n_pad = round_up(n, (int64_t)kWave * g.rpl);
   g.p = p;
   g.p_pad = round_up(p, kGroup);
-  g.ldb = round_up(fmt_col_bytes(g.fmt, g.n_pad), 256);
+  g.seg_bytes = fmt_col_bytes(g.fmt, (int64_t)kWave * g.rpl);
   ctx->standardize = X->standardize ? 1 : 0;
   hipStream_t s = ctx->s;
   const int64_t ng = g.ngroups();
@@ -228,7 +231,7 @@ static pqr_status create_impl(pqr_ctx* ctx, const pqr_design* X) {
     return PQR_ERR_UNSUPPORTED;
   }
 
-  TRY(dalloc(ctx, &ctx->X, (size_t)(g.p_pad * g.ldb)));
+  TRY(dalloc(ctx, &ctx->X, (size_t)g.store_bytes()));
   g.X = ctx->X;
   HIPCHK(launch_encode(X->data, X->src_fmt, X->ld, g, ctx->X, s));
 
@@ -327,6 +330,8 @@ static pqr_status create_impl(pqr_ctx* ctx, const pqr_design* X) {
   TRY(dalloc(ctx, &ctx->theta, g.n_pad * ts));
   TRY(dalloc(ctx, &ctx->r, g.n_pad * ts));
   TRY(dalloc(ctx, &ctx->bpart, (g.n_pad / 256) * 8 * 8));
+  TRY(dalloc(ctx, &ctx->bcnt, kCompactBlocks * 4));
+  TRY(dalloc(ctx, &ctx->bnrm, kCompactBlocks * 4 * 8));
   TRY(dalloc(ctx, &ctx->ctl, sizeof(Ctl)));
   TRY(dalloc(ctx, &ctx->ctl_kkt, sizeof(Ctl)));
   HIPCHK(hipMemsetAsync(ctx->beta, 0, g.p_pad * ts, s));

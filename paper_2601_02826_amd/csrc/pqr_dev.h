@@ -1,11 +1,11 @@
 // Device-side building blocks of libpqr (gfx950, wave64).
 //
-// Layout of the design store: column-major, one column of p_pad columns per
-// `ldb` bytes, rows padded with zeros to n_pad, a multiple of 64*RPL.  A
-// wavefront reads a "chunk" of 64*RPL rows of one column with each lane
-// holding RPL consecutive rows, so every column read is one contiguous,
-// fully coalesced segment and the lane's RPL values of theta are loaded once
-// and reused across the 16 columns of a column group.
+// Layout of the design store: rows padded with zeros to n_pad, a multiple of
+// 64*RPL, and cut into chunks of 64*RPL rows; a wavefront reads one column's
+// chunk (a "segment") with each lane holding RPL consecutive rows, so every
+// read is contiguous and fully coalesced, and the lane's RPL values of theta
+// are loaded once and reused across the 16 columns of a column group.  The
+// segments of one group and chunk are adjacent in memory (see Geom::seg).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -28,86 +28,125 @@ template <> struct Vec4<float> { using type = float4; };
 template <> struct Vec4<double> { using type = double4; };
 
 // ---------------------------------------------------------------------------
-// Decode RPL consecutive rows of one column starting at row0.
+// Raw loads and decoding of RPL consecutive rows of one column, starting at
+// row offset `row0` inside a segment.  The split lets a wavefront issue the loads of several columns before
+// it decodes any of them (more bytes in flight per wavefront).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float ubyte(uint32_t w, int b) { return (float)((w >> (8 * b)) & 0xffu); }
 
+template <int FMT, int RPL> struct Raw;
+template <> struct Raw<I8, 16> { uint4 v; };
+template <> struct Raw<I8, 4> { uint32_t v; };
+template <> struct Raw<FP8, 16> { uint4 v; };
+template <> struct Raw<FP8, 4> { uint32_t v; };
+template <> struct Raw<BF16, 16> { uint4 v[2]; };
+template <> struct Raw<BF16, 4> { uint2 v; };
+template <> struct Raw<F32, 16> { float4 v[4]; };
+template <> struct Raw<F32, 4> { float4 v; };
+template <> struct Raw<F64, 16> { double2 v[8]; };
+template <> struct Raw<F64, 4> { double2 v[2]; };
+template <> struct Raw<B2, 16> { uint32_t v; };
+
+// columns whose raw loads are kept in flight together (VGPR budget ~64 per lane)
+template <int FMT, int RPL> struct Batch { static constexpr int value = 16; };
+template <> struct Batch<BF16, 16> { static constexpr int value = 8; };
+template <> struct Batch<F32, 16> { static constexpr int value = 4; };
+template <> struct Batch<F64, 16> { static constexpr int value = 2; };
+template <> struct Batch<F32, 4> { static constexpr int value = 16; };
+template <> struct Batch<F64, 4> { static constexpr int value = 8; };
+
+template <int FMT, int RPL>
+__device__ __forceinline__ Raw<FMT, RPL> load_raw(const uint8_t* __restrict__ col, int64_t row0) {
+  Raw<FMT, RPL> r;
+  if constexpr (FMT == I8 || FMT == FP8) {
+    if constexpr (RPL == 16) r.v = *reinterpret_cast<const uint4*>(col + row0);
+    else r.v = *reinterpret_cast<const uint32_t*>(col + row0);
+  } else if constexpr (FMT == BF16) {
+    if constexpr (RPL == 16) {
+      const uint4* p = reinterpret_cast<const uint4*>(col + row0 * 2);
+      r.v[0] = p[0]; r.v[1] = p[1];
+    } else {
+      r.v = *reinterpret_cast<const uint2*>(col + row0 * 2);
+    }
+  } else if constexpr (FMT == F32) {
+    const float4* p = reinterpret_cast<const float4*>(col + row0 * 4);
+    if constexpr (RPL == 16) { r.v[0] = p[0]; r.v[1] = p[1]; r.v[2] = p[2]; r.v[3] = p[3]; }
+    else r.v = p[0];
+  } else if constexpr (FMT == F64) {
+    const double2* p = reinterpret_cast<const double2*>(col + row0 * 8);
+#pragma unroll
+    for (int q = 0; q < RPL / 2; ++q) r.v[q] = p[q];
+  } else {
+    static_assert(FMT == B2 && RPL == 16, "2-bit codes need 16 rows per lane");
+    r.v = *reinterpret_cast<const uint32_t*>(col + row0 / 4);
+  }
+  return r;
+}
+
 template <int FMT, int RPL, typename T>
-__device__ __forceinline__ void load_rows(const uint8_t* __restrict__ col, int64_t row0, T (&x)[RPL]) {
+__device__ __forceinline__ void decode(const Raw<FMT, RPL>& r, T (&x)[RPL]) {
   if constexpr (FMT == I8) {
     if constexpr (RPL == 16) {
-      const uint4 v = *reinterpret_cast<const uint4*>(col + row0);
-      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+      const uint32_t w[4] = {r.v.x, r.v.y, r.v.z, r.v.w};
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int b = 0; b < 4; ++b) x[4 * q + b] = (T)ubyte(w[q], b);
     } else {
-      static_assert(RPL == 4, "I8 supports 4 or 16 rows per lane");
-      const uint32_t w = *reinterpret_cast<const uint32_t*>(col + row0);
 #pragma unroll
-      for (int b = 0; b < 4; ++b) x[b] = (T)ubyte(w, b);
+      for (int b = 0; b < 4; ++b) x[b] = (T)ubyte(r.v, b);
     }
   } else if constexpr (FMT == FP8) {
-    constexpr int NW = RPL / 4;
-    uint32_t w[NW];
-    if constexpr (RPL == 16) {
-      const uint4 v = *reinterpret_cast<const uint4*>(col + row0);
-      w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
-    } else {
-      static_assert(RPL == 4, "FP8 supports 4 or 16 rows per lane");
-      w[0] = *reinterpret_cast<const uint32_t*>(col + row0);
-    }
+    uint32_t w[RPL / 4];
+    if constexpr (RPL == 16) { w[0] = r.v.x; w[1] = r.v.y; w[2] = r.v.z; w[3] = r.v.w; }
+    else w[0] = r.v;
 #pragma unroll
-    for (int q = 0; q < NW; ++q) {
+    for (int q = 0; q < RPL / 4; ++q) {
       const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[q], false);
       const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[q], true);
       x[4 * q + 0] = (T)lo[0]; x[4 * q + 1] = (T)lo[1];
       x[4 * q + 2] = (T)hi[0]; x[4 * q + 3] = (T)hi[1];
     }
   } else if constexpr (FMT == BF16) {
-    constexpr int NW = RPL / 2;
-    uint32_t w[NW];
-    const uint4* p = reinterpret_cast<const uint4*>(col + row0 * 2);
+    uint32_t w[RPL / 2];
     if constexpr (RPL == 16) {
-      const uint4 a = p[0], b = p[1];
-      w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w; w[4] = b.x; w[5] = b.y; w[6] = b.z; w[7] = b.w;
+      w[0] = r.v[0].x; w[1] = r.v[0].y; w[2] = r.v[0].z; w[3] = r.v[0].w;
+      w[4] = r.v[1].x; w[5] = r.v[1].y; w[6] = r.v[1].z; w[7] = r.v[1].w;
     } else {
-      static_assert(RPL == 4, "BF16 supports 4 or 16 rows per lane");
-      const uint2 a = *reinterpret_cast<const uint2*>(col + row0 * 2);
-      w[0] = a.x; w[1] = a.y;
+      w[0] = r.v.x; w[1] = r.v.y;
     }
 #pragma unroll
-    for (int q = 0; q < NW; ++q) {
+    for (int q = 0; q < RPL / 2; ++q) {
       x[2 * q + 0] = (T)__uint_as_float(w[q] << 16);
       x[2 * q + 1] = (T)__uint_as_float(w[q] & 0xffff0000u);
     }
   } else if constexpr (FMT == F32) {
-    const float4* p = reinterpret_cast<const float4*>(col + row0 * 4);
+    if constexpr (RPL == 16) {
 #pragma unroll
-    for (int q = 0; q < RPL / 4; ++q) {
-      const float4 v = p[q];
-      x[4 * q + 0] = (T)v.x; x[4 * q + 1] = (T)v.y; x[4 * q + 2] = (T)v.z; x[4 * q + 3] = (T)v.w;
+      for (int q = 0; q < 4; ++q) {
+        x[4 * q + 0] = (T)r.v[q].x; x[4 * q + 1] = (T)r.v[q].y;
+        x[4 * q + 2] = (T)r.v[q].z; x[4 * q + 3] = (T)r.v[q].w;
+      }
+    } else {
+      x[0] = (T)r.v.x; x[1] = (T)r.v.y; x[2] = (T)r.v.z; x[3] = (T)r.v.w;
     }
   } else if constexpr (FMT == F64) {
-    const double2* p = reinterpret_cast<const double2*>(col + row0 * 8);
 #pragma unroll
-    for (int q = 0; q < RPL / 2; ++q) {
-      const double2 v = p[q];
-      x[2 * q + 0] = (T)v.x; x[2 * q + 1] = (T)v.y;
-    }
+    for (int q = 0; q < RPL / 2; ++q) { x[2 * q] = (T)r.v[q].x; x[2 * q + 1] = (T)r.v[q].y; }
   } else {
-    static_assert(FMT == B2, "unknown format");
-    static_assert(RPL == 16, "2-bit codes need 16 rows per lane");
     // one 32-bit word = 16 rows; byte b holds rows 4b..4b+3, row 4b+k in bits 2k..2k+1
-    const uint32_t w = *reinterpret_cast<const uint32_t*>(col + row0 / 4);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const uint32_t t = (w >> (2 * k)) & 0x03030303u;
+      const uint32_t t = (r.v >> (2 * k)) & 0x03030303u;
 #pragma unroll
       for (int b = 0; b < 4; ++b) x[4 * b + k] = (T)ubyte(t, b);
     }
   }
+}
+
+template <int FMT, int RPL, typename T>
+__device__ __forceinline__ void load_rows(const uint8_t* __restrict__ col, int64_t row0, T (&x)[RPL]) {
+  decode<FMT, RPL, T>(load_raw<FMT, RPL>(col, row0), x);
 }
 
 template <int RPL, typename T>

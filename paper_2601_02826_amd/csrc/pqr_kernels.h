@@ -8,15 +8,25 @@
 namespace pqr {
 
 // Geometry of the design store shared by every kernel.
+//
+// The store is blocked by (column group, row chunk): a "segment" holds one
+// column's 64*rpl consecutive rows (a wavefront's load), and the 16 segments of
+// a group for one chunk are contiguous, so a wavefront sweeping a group streams
+// one contiguous run of 16 segments per chunk.  Segment of column j, chunk ch:
+//     X + ((j/16 * nchunks + ch) * 16 + j%16) * seg_bytes.
 struct Geom {
   const uint8_t* X;   // store base
   int fmt;            // Fmt
   int rpl;            // rows per lane: 4 or 16
   int64_t n, n_pad;   // rows, padded rows (multiple of 64*rpl)
   int64_t p, p_pad;   // feature columns, padded to a multiple of kGroup
-  int64_t ldb;        // bytes per stored column
+  int64_t seg_bytes;  // bytes of one segment (64*rpl rows of one column)
   __host__ __device__ int64_t ngroups() const { return p_pad / kGroup; }
   __host__ __device__ int64_t nchunks() const { return n_pad / (kWave * rpl); }
+  __host__ __device__ int64_t store_bytes() const { return p_pad * nchunks() * seg_bytes; }
+  __host__ __device__ const uint8_t* seg(int64_t j, int64_t ch) const {
+    return X + (((j >> 4) * nchunks() + ch) * kGroup + (j & 15)) * seg_bytes;
+  }
 };
 
 template <typename T>
@@ -35,8 +45,12 @@ struct IterBufs {
   T* theta;       // n_pad (padding rows stay 0)
   T* r;           // n_pad cached residual X~beta + z - y
   double* bpart;  // update-kernel block partials (nblk x 8)
+  int* bcnt;      // kCompactBlocks active-group counts of the compaction
+  double* bnrm;   // kCompactBlocks x 4 norm partials of the compaction
   Ctl* ctl;
 };
+
+constexpr int kCompactBlocks = 64;
 
 struct IterParams {
   double tau, mu, sigma, eta0;
