@@ -78,7 +78,9 @@ typedef struct {
   double mu_scale;      /* default 0.1                                         */
   int G;                /* number of column blocks (decomposition of X); default 48,
                            capped at ceil(p/16); block boundaries are multiples of 16 */
-  double eta_margin;    /* eta_g = (1 + margin) * mu * Lambda_g; default 0.01  */
+  double eta_margin;    /* eta_g = (1 + margin) * mu * Lambda_g; default 0.01; a value in
+                           (-1, 0) violates eta_g > mu Lambda_max on purpose (to exercise
+                           the monitor that doubles eta and reports PQR_ERR_DIVERGED) */
   int lanczos_steps;    /* steps of the Lanczos estimate of Lambda_g; default 40 */
   int iter_prec;        /* pqr_iter_prec; default PQR_ITER_F32                 */
   double tol_gap;       /* stop when the FP64 relative duality gap <= tol_gap; default 1e-6 */

@@ -18,12 +18,18 @@ namespace pqr {
 
 template <typename T> __device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
 
+// Column dot products of one 16-column group with theta.  Each lane sums its
+// rows of two chunks in the iterate type and adds that partial to an FP64
+// accumulator; the cross-lane reduction is FP64 too, so the FP32 path's
+// x~_j^T theta is accurate to the FP32 rounding of theta rather than limited by
+// the cancellation of n FP32 products.
 template <int FMT, int RPL, typename T>
 __device__ __forceinline__ void group_dots(const Geom& g, int64_t grp, const T* __restrict__ theta,
-                                           T (&acc)[kGroup]) {
+                                           double (&accd)[kGroup]) {
   const int lane = threadIdx.x & 63;
+  T acc[kGroup];
 #pragma unroll
-  for (int c = 0; c < kGroup; ++c) acc[c] = 0;
+  for (int c = 0; c < kGroup; ++c) { accd[c] = 0; acc[c] = 0; }
   const int64_t nch = g.nchunks();
   const int64_t lrow = (int64_t)lane * RPL;
   constexpr int B = Batch<FMT, RPL>::value;
@@ -45,6 +51,10 @@ __device__ __forceinline__ void group_dots(const Geom& g, int64_t grp, const T* 
         for (int r = 0; r < RPL; ++r) acc[cb + c] = fma(x[r], th[r], acc[cb + c]);
       }
     }
+    if ((ch & 1) || ch + 1 == nch) {   // flush every two chunks (2*RPL rows per lane)
+#pragma unroll
+      for (int c = 0; c < kGroup; ++c) { accd[c] += (double)acc[c]; acc[c] = 0; }
+    }
   }
 }
 
@@ -54,14 +64,14 @@ __global__ __launch_bounds__(256) void k_sweep(Geom g, IterBufs<T> b) {
   const int lane = threadIdx.x & 63;
   const int64_t grp = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (grp >= g.ngroups()) return;
-  T acc[kGroup];
+  double acc[kGroup];
   group_dots<FMT, RPL, T>(g, grp, b.theta, acc);
-  const T dot = reduce16(acc, lane);
+  const double dot = reduce16(acc, lane);
 
   const int64_t j = grp * kGroup + group_col_of_lane(lane);
   const bool owner = (lane & 3) == 0;
-  const T st = (T)b.ctl->sum_theta;
-  const T v = (dot - b.cm[j] * st) * b.cinv[j];   // x~_j^T theta on the standardized scale
+  // x~_j^T theta on the standardized scale
+  const T v = (T)((dot - (double)b.cm[j] * b.ctl->sum_theta) * (double)b.cinv[j]);
   const T bo = b.beta[j];
   const T eta = b.geta[grp];
   const T lam = b.clam[j];
@@ -195,25 +205,25 @@ __global__ __launch_bounds__(256) void k_axpy(Geom g, IterBufs<T> b, int smax, i
   const int e0 = split * per;
   const int e1 = e0 + per < count ? e0 + per : count;
   const int64_t row0 = ch * (kWave * RPL) + (int64_t)lane * RPL;
-  T acc[RPL];
+  double acc[RPL];
 #pragma unroll
   for (int r = 0; r < RPL; ++r) acc[r] = 0;
-  T off = 0;
+  double off = 0;
   for (int e = e0; e < e1; ++e) {
     const int64_t grp = b.list[e];
     for (int c = 0; c < kGroup; ++c) {
       const int64_t j = grp * kGroup + c;
-      const T bj = b.beta[j] * b.cinv[j];   // coefficient on the raw column
-      if (bj != T(0)) {
-        T x[RPL];
-        load_rows<FMT, RPL, T>(g.seg(j, ch), (int64_t)lane * RPL, x);
+      const double bj = (double)b.beta[j] * (double)b.cinv[j];   // coefficient on the raw column
+      if (bj != 0.0) {
+        double x[RPL];
+        load_rows<FMT, RPL, double>(g.seg(j, ch), (int64_t)lane * RPL, x);
 #pragma unroll
         for (int r = 0; r < RPL; ++r) acc[r] = fma(x[r], bj, acc[r]);
-        off = fma(b.cm[j], bj, off);
+        off = fma((double)b.cm[j], bj, off);
       }
     }
   }
-  T* out = b.partial + (int64_t)split * g.n_pad + row0;
+  double* out = b.partial + (int64_t)split * g.n_pad + row0;
 #pragma unroll
   for (int r = 0; r < RPL; ++r) out[r] = acc[r] - off;
 }
@@ -228,14 +238,14 @@ __global__ __launch_bounds__(256) void k_update(IterBufs<T> b, IterParams ip, in
   const int seff = splits_in_use(b.ctl->count, ip.smax, ip.min_per);
   double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (i < n) {
-    T s = (T)b.ctl->beta0;
+    double s = b.ctl->beta0;
     for (int k = 0; k < seff; ++k) s += b.partial[(int64_t)k * n_pad + i];
     const T mu = (T)ip.mu;
     const T zo = b.z[i], to = b.theta[i], ro = b.r[i];
     const T u = zo + to / mu;
     const T zn = tmax<T>(u - (T)(ip.tau / ((double)n * ip.mu)), 0) -
                  tmax<T>(-u - (T)((1.0 - ip.tau) / ((double)n * ip.mu)), 0);   // eq. z_update
-    const T rn = s + zn - b.y[i];
+    const T rn = (T)(s + (double)zn - (double)b.y[i]);
     const T tn = to - (T)ip.sigma * ((T)2 * rn - ro);                         // dual step
     b.z[i] = zn;
     b.theta[i] = tn;
@@ -284,9 +294,9 @@ __global__ __launch_bounds__(256) void k_init_r(IterBufs<T> b, IterParams ip, in
   const int seff = splits_in_use(b.ctl->count, ip.smax, ip.min_per);
   double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (i < n) {
-    T s = (T)b.ctl->beta0;
+    double s = b.ctl->beta0;
     for (int k = 0; k < seff; ++k) s += b.partial[(int64_t)k * n_pad + i];
-    b.r[i] = s + b.z[i] - b.y[i];
+    b.r[i] = (T)(s + (double)b.z[i] - (double)b.y[i]);
     q[6] = (double)b.theta[i];
   }
   block_sum<256, 8, double>(q, red);

@@ -155,7 +155,7 @@ IterBufs<T> bufs(pqr_ctx* ctx) {
   b.gnorm = (T*)ctx->gnorm;
   b.gflag = ctx->gflag;
   b.list = ctx->list;
-  b.partial = (T*)ctx->partial;
+  b.partial = (double*)ctx->partial;
   b.y = (const T*)ctx->y_t;
   b.z = (T*)ctx->z;
   b.theta = (T*)ctx->theta;
@@ -324,7 +324,7 @@ static pqr_status create_impl(pqr_ctx* ctx, const pqr_design* X) {
   TRY(dalloc(ctx, &ctx->gnorm, ng * 4 * ts));
   TRY(dalloc(ctx, &ctx->gflag, ng * 4));
   TRY(dalloc(ctx, &ctx->list, ng * 4));
-  TRY(dalloc(ctx, &ctx->partial, (size_t)ctx->smax * g.n_pad * ts));
+  TRY(dalloc(ctx, &ctx->partial, (size_t)ctx->smax * g.n_pad * 8));
   TRY(dalloc(ctx, &ctx->y_t, g.n_pad * ts));
   TRY(dalloc(ctx, &ctx->z, g.n_pad * ts));
   TRY(dalloc(ctx, &ctx->theta, g.n_pad * ts));
@@ -373,7 +373,9 @@ extern "C" pqr_status pqr_create(pqr_ctx** out, const pqr_design* X, const pqr_o
   pqr_options d;
   pqr_default_options(&d);
   if (ctx->opt.mu_scale <= 0) ctx->opt.mu_scale = d.mu_scale;
-  if (ctx->opt.eta_margin <= 0) ctx->opt.eta_margin = d.eta_margin;
+  // a negative margin (> -1) puts eta below mu*Lambda on purpose: it exists to
+  // exercise the H-norm monitor; 0 selects the default
+  if (ctx->opt.eta_margin == 0 || ctx->opt.eta_margin <= -1) ctx->opt.eta_margin = d.eta_margin;
   if (ctx->opt.tol_gap <= 0) ctx->opt.tol_gap = d.tol_gap;
   if (ctx->opt.cert_every <= 0) ctx->opt.cert_every = d.cert_every;
   if (ctx->opt.max_iter <= 0) ctx->opt.max_iter = d.max_iter;

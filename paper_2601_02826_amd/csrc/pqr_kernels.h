@@ -39,7 +39,7 @@ struct IterBufs {
   T* gnorm;       // ngroups x 4 sweep partials
   int* gflag;     // ngroups: 1 if any coefficient of the group is nonzero
   int* list;      // ngroups: active groups in increasing order (first ctl->count)
-  T* partial;     // smax x n_pad partial products
+  double* partial;  // smax x n_pad partial products (FP64 for every iterate type)
   const T* y;     // n_pad
   T* z;           // n_pad
   T* theta;       // n_pad (padding rows stay 0)
