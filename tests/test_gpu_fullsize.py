@@ -1,0 +1,127 @@
+"""Parity at the benchmark's full size (n = 20,000, p = 1,000,000 int8 dosages, 12
+feature blocks), on outputs the oracle can compute column by column: the null-fit
+scores, one Algorithm 1 step on sampled columns, and the objective and dual
+feasibility of a solved point."""
+import numpy as np
+import pytest
+
+from datagen.configs import SPECS, genotype_columns, make_genotype
+from oracle import pqr
+
+pytestmark = pytest.mark.gpu
+
+N, P, G = 20_000, 1_000_000, 12
+
+
+@pytest.fixture(scope="module")
+def full():
+    import torch
+    import paper_2601_02826_amd as pq
+    from datagen import native
+    spec = SPECS["geno_20kx1M"]
+    assert (spec.n, spec.p) == (N, P)
+    g = make_genotype(spec, with_X=False)
+    thr = torch.from_numpy(g["thr"].astype(np.int64)).to(torch.int32).cuda()
+    Xc = torch.empty((P, N), dtype=torch.uint8, device="cuda")
+    native.genotype_device(Xc.data_ptr(), N, N, P, thr.data_ptr(), spec.seed, spec.tag,
+                           torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    ctx = pq.Context.from_tensor(Xc, store_fmt="i8", standardize=True, G=G, tol_gap=1e-3,
+                                 cert_every=50, max_iter=20000)
+    ctx._keep = None
+    del Xc
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(0)
+    sample = np.sort(rng.choice(P, 400, replace=False))
+    yield spec, g, ctx, sample
+    ctx.close()
+
+
+def _std_cols(spec, cols):
+    """Oracle standardization of the given columns from their own exact statistics."""
+    X = genotype_columns(spec, cols).astype(np.float64)
+    Xt, m, s = pqr.standardize(X)
+    return Xt
+
+
+def test_device_generator_matches_host_definition(full):
+    import torch
+    from datagen import native
+    spec, g, ctx, sample = full
+    cols = sample[:32]
+    thr = torch.from_numpy(g["thr"][cols].astype(np.int64)).to(torch.int32).cuda()
+    out = torch.empty((len(cols), N), dtype=torch.uint8, device="cuda")
+    for k, j in enumerate(cols):   # one column at a time through the device twin
+        native.genotype_device(out[k].data_ptr(), N, N, 1, thr[k:k + 1].data_ptr(), spec.seed,
+                               spec.tag, torch.cuda.current_stream().cuda_stream, j0=int(j))
+    torch.cuda.synchronize()
+    want = genotype_columns(spec, cols)
+    assert np.array_equal(out.cpu().numpy().T.astype(np.int8), want)
+
+
+def test_scores_on_sampled_columns(full):
+    spec, g, ctx, sample = full
+    y = g["y"]
+    lmax, score = ctx.lambda_max(y, 0.5, score=True)
+    _, psi = pqr.null_dual(y, 0.5)
+    Xt = _std_cols(spec, sample)
+    want = Xt.T @ psi / N
+    assert np.allclose(score[sample], want, rtol=1e-10, atol=1e-15)
+    assert lmax >= np.max(np.abs(want)) * (1 - 1e-12)
+    assert lmax == pytest.approx(np.max(np.abs(score)), rel=1e-14)
+
+
+def test_one_step_on_sampled_columns(full):
+    spec, g, ctx, sample = full
+    y = g["y"]
+    tau = 0.5
+    lmax = ctx.lambda_max(y, tau)
+    lam = 0.3 * lmax
+    rng = np.random.default_rng(1)
+    beta = np.zeros(P + 1)
+    beta[0] = 0.2
+    nzc = rng.choice(P, 50, replace=False)
+    beta[1 + nzc] = rng.standard_normal(50) * 0.01
+    z = rng.standard_normal(N) * 0.3
+    theta = (rng.random(N) - 0.5) / N
+    Gt, bounds, Lam = ctx.blocks()
+    mu = 1e-5
+    eta = 1.01 * mu * Lam
+    b1, z1, t1 = ctx.iterate(y, tau, lam, mu, eta, 1, beta, z, theta)
+    # z only depends on (z, theta): every row is checkable; FP32 rounds the prox
+    # argument u = z + theta/mu and the thresholds, so the bound is a few FP32 ulps of
+    # |z| + |theta/mu| + 1/(n mu)
+    bound = 8 * np.finfo(np.float32).eps * (np.abs(z) + np.abs(theta / mu) + 1 / (N * mu))
+    assert np.all(np.abs(z1 - pqr.z_prox(z, theta, tau, N, mu)) <= bound)
+    # beta on sampled columns: v_j = x~_j^T theta from the oracle's columns
+    Xt = _std_cols(spec, sample)
+    v = Xt.T @ theta
+    blk = np.searchsorted(bounds[1:], sample, side="right")    # feature block of each column
+    eta_j = eta[blk]
+    want = pqr.beta_prox(beta[1 + sample], v, np.full(len(sample), lam), eta_j)
+    assert np.allclose(b1[1 + sample], want, rtol=1e-5, atol=1e-9)
+    # intercept (its own block 0): beta0 + sum(theta) / eta_0
+    assert b1[0] == pytest.approx(beta[0] + theta.sum() / eta[0], rel=1e-6)
+
+
+def test_solved_point_objective_and_dual_feasibility(full):
+    spec, g, ctx, sample = full
+    y = g["y"]
+    tau = 0.5
+    lmax = ctx.lambda_max(y, tau)
+    lam = 0.5 * lmax
+    r = ctx.solve(y, tau, lam)
+    assert r["rel_gap"] <= 1e-3
+    support = np.nonzero(r["beta_std"][1:])[0]
+    assert 0 < len(support) < 500
+    Xs = _std_cols(spec, support)
+    fit = r["beta_std"][0] + Xs @ r["beta_std"][1 + support]
+    primal = np.mean(pqr.pinball(y - fit, tau)) + lam * np.abs(r["beta_std"][1 + support]).sum()
+    assert r["primal"] == pytest.approx(primal, rel=1e-10)
+    # dual side on the support and the sample: the projected theta's ratios never exceed
+    # the device-wide maximum implied by the reported dual value
+    tp = pqr.project_box_sum(r["theta"], (tau - 1) / N, tau / N)
+    cols = np.union1d(support, sample)
+    ratios = np.abs(_std_cols(spec, cols).T @ tp) / lam
+    assert np.all(ratios <= 1.0 + 5e-2)
+    assert np.max(ratios[np.isin(cols, support)]) > 0.9
