@@ -92,6 +92,8 @@ typedef struct {
                            Lambda = n) and the G feature blocks follow; 0 = the
                            intercept is the first column of the first feature block.
                            Set through pqr_default_options; 0 is honoured as given. */
+  int rows_per_lane;    /* 0 = automatic (16 when n >= 8192 or for 2-bit, else 4); 4 or 16
+                           forces the row geometry (the batched solver needs 16) */
 } pqr_options;
 
 typedef struct pqr_ctx pqr_ctx;
@@ -179,6 +181,21 @@ pqr_status pqr_blocks(pqr_ctx* ctx, int* G, int* bounds, double* Lambda);
 pqr_status pqr_iterate(pqr_ctx* ctx, const double* y, double tau, double lambda,
                        const double* weights, double mu, const double* eta, int64_t iters,
                        double* beta_std, double* z, double* theta);
+
+/* K problems that share X, y and the weights, with their own (tau_k, lambda_k),
+ * solved together (Algorithm 1 for every k, iterated in lockstep).  The back-
+ * products X~^T Theta of all k run on the int8 matrix cores over digit slices of
+ * theta (exact integer arithmetic); every k is stopped by its own FP64 duality-gap
+ * certificate (pqr_kkt's).  Needs an int8 store, rows_per_lane 16 and FP32
+ * iterates (PQR_ERR_UNSUPPORTED otherwise); 1 <= K <= 128.
+ *  y, weights  as in pqr_solve;  taus, lambdas  host, K doubles each
+ *  outs        host array of K pqr_result (output arrays optional, as in pqr_solve);
+ *              beta/z/theta are the final iterate, rel_gap its certified gap
+ * Returns PQR_ERR_NOT_CONVERGED (outputs filled) if max_iter ends the solve first.
+ * The single right-hand-side device state is discarded (PQR_START_DEVICE needs a
+ * new pqr_solve afterwards). */
+pqr_status pqr_solve_batch(pqr_ctx* ctx, const double* y, int K, const double* taus,
+                           const double* lambdas, const double* weights, pqr_result* outs);
 
 void pqr_destroy(pqr_ctx* ctx);
 const char* pqr_last_error(const pqr_ctx* ctx);

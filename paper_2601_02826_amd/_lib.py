@@ -33,7 +33,7 @@ class pqr_options(ctypes.Structure):
                 ("iter_prec", ctypes.c_int), ("tol_gap", ctypes.c_double),
                 ("cert_every", ctypes.c_int), ("max_iter", ctypes.c_int64),
                 ("stream", ctypes.c_void_p), ("profile", ctypes.c_int),
-                ("intercept_block", ctypes.c_int)]
+                ("intercept_block", ctypes.c_int), ("rows_per_lane", ctypes.c_int)]
 
 
 class pqr_result(ctypes.Structure):
@@ -47,7 +47,8 @@ class pqr_result(ctypes.Structure):
 
 
 SYMBOLS = ["pqr_default_options", "pqr_create", "pqr_solve", "pqr_kkt", "pqr_lambda_max",
-           "pqr_blocks", "pqr_iterate", "pqr_destroy", "pqr_last_error", "pqr_status_string"]
+           "pqr_blocks", "pqr_iterate", "pqr_solve_batch", "pqr_destroy", "pqr_last_error",
+           "pqr_status_string"]
 
 _lib = None
 
@@ -77,6 +78,8 @@ def load():
     lib.pqr_blocks.restype = ci
     lib.pqr_iterate.argtypes = [vp, _c_dp, dbl, dbl, _c_dp, dbl, _c_dp, i64, _c_dp, _c_dp, _c_dp]
     lib.pqr_iterate.restype = ci
+    lib.pqr_solve_batch.argtypes = [vp, _c_dp, ci, _c_dp, _c_dp, _c_dp, ctypes.POINTER(pqr_result)]
+    lib.pqr_solve_batch.restype = ci
     lib.pqr_destroy.argtypes = [vp]
     lib.pqr_destroy.restype = None
     lib.pqr_last_error.argtypes = [vp]
@@ -206,6 +209,33 @@ class Context:
                       dual=out.dual, rel_gap=out.rel_gap, lambda_max=out.lambda_max, mu=out.mu,
                       seconds=out.seconds, sweep_ms=out.sweep_ms,
                       sweep_launches=out.sweep_launches, status=st)
+
+    def solve_batch(self, y, taus, lams, weights=None, allow_not_converged=False):
+        """pqr_solve_batch: K (tau_k, lambda_k) pairs on the same X and y."""
+        taus = _f64(taus)
+        lams = _f64(lams)
+        K = len(taus)
+        if len(lams) != K:
+            raise ValueError("taus and lams differ in length")
+        outs = (pqr_result * K)()
+        keep = []
+        for k in range(K):
+            arr = dict(beta=np.zeros(self.p + 1), beta_std=np.zeros(self.p + 1),
+                       z=np.zeros(self.n), theta=np.zeros(self.n))
+            keep.append(arr)
+            outs[k].beta, outs[k].beta_std = _dptr(arr["beta"]), _dptr(arr["beta_std"])
+            outs[k].z, outs[k].theta = _dptr(arr["z"]), _dptr(arr["theta"])
+        st = self._lib.pqr_solve_batch(self._h, _dptr(_f64(y, self.n)), K, _dptr(taus), _dptr(lams),
+                                       _dptr(_f64(weights, self.p + 1)), outs)
+        ok = (PQR_OK, PQR_ERR_NOT_CONVERGED) if allow_not_converged else (PQR_OK,)
+        self._check(st, ok)
+        res = []
+        for k in range(K):
+            o = outs[k]
+            res.append(Result(**keep[k], iters=o.iters, x_passes=o.x_passes, certs=o.certs,
+                              nnz=o.nnz, primal=o.primal, dual=o.dual, rel_gap=o.rel_gap,
+                              mu=o.mu, seconds=o.seconds, status=st))
+        return res
 
     def kkt(self, y, tau, lam, beta_std, theta, weights=None):
         rep = np.zeros(4)

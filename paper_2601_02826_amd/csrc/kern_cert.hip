@@ -279,6 +279,16 @@ __global__ __launch_bounds__(256) void k_final_max(const double* bpart, int64_t 
   if (threadIdx.x == 0) *out = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
+__global__ __launch_bounds__(256) void k_scale(const double* w, double a, int64_t m, double* out) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256)
+    out[i] = a * w[i];
+}
+
+hipError_t launch_scale(const double* w, double a, int64_t m, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale, dim3(1024), dim3(256), 0, s, w, a, m, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_reduce_sum(const double* a, int64_t m, double* bpart, double* out,
                              hipStream_t s) {
   const unsigned nb = 256;

@@ -378,6 +378,17 @@ hipError_t launch_prepare_state(const Geom& g, const IterBufs<T>& b, const IterP
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_active_list(const Geom& g, const IterBufs<T>& b, hipStream_t s) {
+  const int64_t ng = g.ngroups();
+  hipLaunchKernelGGL((k_flags<T>), dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, s, ng, b);
+  hipLaunchKernelGGL((k_count<T>), dim3(kCompactBlocks), dim3(1024), 0, s, ng, b);
+  hipLaunchKernelGGL((k_scatter<T>), dim3(kCompactBlocks), dim3(1024), 0, s, ng, b, 1.0, 0);
+  return hipGetLastError();
+}
+template hipError_t launch_active_list<float>(const Geom&, const IterBufs<float>&, hipStream_t);
+template hipError_t launch_active_list<double>(const Geom&, const IterBufs<double>&, hipStream_t);
+
 template hipError_t launch_iteration<float>(const Geom&, const IterBufs<float>&, const IterParams&, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_iteration<double>(const Geom&, const IterBufs<double>&, const IterParams&, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_prepare_state<float>(const Geom&, const IterBufs<float>&, const IterParams&, hipStream_t);

@@ -58,6 +58,10 @@ struct pqr_ctx {
   double state_mu = 0.0;
   std::vector<void*> allocs;
   std::vector<hipEvent_t> events;   // 2 per iteration of a chunk when profiling
+  int batch_kp = 0;                 // capacity of the batched buffers (right-hand sides)
+  BatchBufs bb{};
+  double* w_d = nullptr;            // p_pad penalty weights in FP64 (batched certificates)
+  float* yb = nullptr;              // n_pad y in FP32 (batched iterations)
 };
 
 namespace {
@@ -218,6 +222,8 @@ static pqr_status create_impl(pqr_ctx* ctx, const pqr_design* X) {
   Geom& g = ctx->g;
   g.fmt = X->store_fmt;
   g.rpl = (g.fmt == B2 || n >= 8192) ? 16 : 4;
+  if (ctx->opt.rows_per_lane == 16) g.rpl = 16;
+  else if (ctx->opt.rows_per_lane == 4 && g.fmt != B2) g.rpl = 4;
   g.n = n;
   g.n_pad = round_up(n, (int64_t)kWave * g.rpl);
   g.p = p;
@@ -534,16 +540,18 @@ struct Cert {
   double primal, dual, gap, rel_gap, maxratio;
 };
 
+// FP64 certificate of the point (beta, beta0 = ctl->beta0, theta); `list` and
+// ctl->count must describe the nonzero groups of beta; ctx->clam_d holds lambda_j.
 template <typename T>
-pqr_status certificate(pqr_ctx* ctx, double tau, Cert* out) {
+pqr_status certify_point(pqr_ctx* ctx, double tau, const T* theta, const T* beta, const Ctl* ctl,
+                         const int* list, Cert* out) {
   const Geom& g = ctx->g;
   hipStream_t s = ctx->s;
-  HIPCHK(launch_project<T>((const T*)ctx->theta, g.n, g.n_pad, tau, ctx->y_d, ctx->theta_p,
-                           ctx->out_d, s));
+  HIPCHK(launch_project<T>(theta, g.n, g.n_pad, tau, ctx->y_d, ctx->theta_p, ctx->out_d, s));
   HIPCHK(launch_dots64(g, ctx->theta_p, ctx->out_d + 5, ctx->cm_d, ctx->cinv_d, ctx->clam_d,
                        nullptr, ctx->gpart, s));
   HIPCHK(launch_reduce_max(ctx->gpart, g.ngroups(), ctx->bpart64, ctx->out_d + 3, s));
-  HIPCHK(launch_to_double<T>((const T*)ctx->beta, g.p_pad, ctx->beta_d, s));
+  HIPCHK(launch_to_double<T>(beta, g.p_pad, ctx->beta_d, s));
   CertBufs c{};
   c.y = ctx->y_d;
   c.theta_p = ctx->theta_p;
@@ -552,8 +560,8 @@ pqr_status certificate(pqr_ctx* ctx, double tau, Cert* out) {
   c.cinv = ctx->cinv_d;
   c.clam = ctx->clam_d;
   c.partial = ctx->partial64;
-  c.list = ctx->list;
-  c.ctl = ctx->ctl;
+  c.list = list;
+  c.ctl = ctl;
   c.bpart = ctx->bpart64;
   c.out = ctx->out_d;
   HIPCHK(launch_primal64(g, c, tau, ctx->smax, ctx->min_per, s));
@@ -568,6 +576,12 @@ pqr_status certificate(pqr_ctx* ctx, double tau, Cert* out) {
   out->rel_gap = out->gap / std::max(std::fabs(out->primal), 1e-300);
   out->maxratio = mr;
   return PQR_OK;
+}
+
+template <typename T>
+pqr_status certificate(pqr_ctx* ctx, double tau, Cert* out) {
+  return certify_point<T>(ctx, tau, (const T*)ctx->theta, (const T*)ctx->beta, ctx->ctl,
+                          ctx->list, out);
 }
 
 // Copies the coefficients `bsrc` (intercept beta0) and the current z, theta out.
@@ -878,4 +892,200 @@ extern "C" pqr_status pqr_blocks(pqr_ctx* ctx, int* G, int* bounds, double* Lamb
   if (bounds) std::memcpy(bounds, ctx->bounds.data(), (ctx->G + 1) * sizeof(int));
   if (Lambda) std::memcpy(Lambda, ctx->Lambda.data(), ctx->G * sizeof(double));
   return PQR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched right-hand sides
+// ---------------------------------------------------------------------------
+namespace {
+
+pqr_status batch_alloc(pqr_ctx* ctx, int Kp) {
+  if (ctx->batch_kp >= Kp) return PQR_OK;
+  const Geom& g = ctx->g;
+  BatchBufs& b = ctx->bb;
+  const int64_t nblk = g.n_pad / 256, ng = g.ngroups();
+  const int smax = 16;
+  TRY(dalloc(ctx, &b.beta, (size_t)Kp * g.p_pad * 4));
+  float* w;
+  TRY(dalloc(ctx, &w, g.p_pad * 4));
+  b.w = w;
+  float *lam, *tau, *geta;
+  TRY(dalloc(ctx, &lam, Kp * 4));
+  TRY(dalloc(ctx, &tau, Kp * 4));
+  TRY(dalloc(ctx, &geta, ng * 4));
+  b.lam = lam; b.tau = tau; b.geta = geta;
+  if (!ctx->yb) TRY(dalloc(ctx, &ctx->yb, g.n_pad * 4));
+  if (!ctx->w_d) TRY(dalloc(ctx, &ctx->w_d, g.p_pad * 8));
+  b.y = ctx->yb;
+  TRY(dalloc(ctx, &b.z, (size_t)Kp * g.n_pad * 4));
+  TRY(dalloc(ctx, &b.theta, (size_t)Kp * g.n_pad * 4));
+  TRY(dalloc(ctx, &b.r, (size_t)Kp * g.n_pad * 4));
+  TRY(dalloc(ctx, &b.dig, (size_t)3 * Kp * g.n_pad));
+  TRY(dalloc(ctx, &b.tpart, (size_t)nblk * Kp * 8));
+  TRY(dalloc(ctx, &b.tsumq, Kp * 8));
+  TRY(dalloc(ctx, &b.tsum, Kp * 8));
+  TRY(dalloc(ctx, &b.scale, Kp * 8));
+  TRY(dalloc(ctx, &b.beta0, Kp * 8));
+  TRY(dalloc(ctx, &b.norms, Kp * 4 * 8));
+  TRY(dalloc(ctx, &b.mask, (size_t)ng * (Kp / 16) * 4));
+  TRY(dalloc(ctx, &b.list, ng * 4));
+  TRY(dalloc(ctx, &b.bcnt, kCompactBlocks * 4));
+  TRY(dalloc(ctx, &b.count, 64));
+  TRY(dalloc(ctx, &b.partial, (size_t)smax * Kp * g.n_pad * 8));
+  TRY(dalloc(ctx, &b.bpart, (size_t)nblk * Kp * 8 * 8));
+  b.cm = ctx->cm_f;
+  b.cinv = ctx->cinv_f;
+  ctx->batch_kp = Kp;
+  return PQR_OK;
+}
+
+pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
+                      const double* lambdas, const double* weights, pqr_result* outs) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const Geom& g = ctx->g;
+  hipStream_t s = ctx->s;
+  if (g.fmt != I8 || g.rpl != 16 || ctx->opt.iter_prec != PQR_ITER_F32) {
+    ctx->err = "batched solves need an int8 store, rows_per_lane 16 and FP32 iterates";
+    return PQR_ERR_UNSUPPORTED;
+  }
+  if (K < 1 || K > 128 || !taus || !lambdas) {
+    ctx->err = "batched solves take 1 <= K <= 128 (tau_k, lambda_k) pairs";
+    return PQR_ERR_INVALID_ARG;
+  }
+  for (int k = 0; k < K; ++k) TRY(validate_problem(ctx, y, taus[k], lambdas[k], weights));
+  const int Kp = (K + 15) / 16 * 16;
+  TRY(batch_alloc(ctx, Kp));
+  BatchBufs b = ctx->bb;
+  b.K = K;
+  const int64_t ng = g.ngroups();
+  // inputs
+  std::vector<double> yh(g.n_pad, 0.0);
+  std::memcpy(yh.data(), y, g.n * 8);
+  HIPCHK(hipMemcpyAsync(ctx->y_d, yh.data(), g.n_pad * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(launch_set_y<float>(ctx->y_d, g.n, g.n_pad, ctx->yb, s));
+  std::vector<double> wh(g.p_pad, 0.0);
+  std::vector<float> wf(g.p_pad, 0.f);
+  for (int64_t j = 0; j < g.p; ++j) { wh[j] = weights ? weights[1 + j] : 1.0; wf[j] = (float)wh[j]; }
+  HIPCHK(hipMemcpyAsync(ctx->w_d, wh.data(), g.p_pad * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync((void*)b.w, wf.data(), g.p_pad * 4, hipMemcpyHostToDevice, s));
+  std::vector<float> lf(Kp, 0.f), tf(Kp, 0.5f);
+  for (int k = 0; k < K; ++k) { lf[k] = (float)lambdas[k]; tf[k] = (float)taus[k]; }
+  HIPCHK(hipMemcpyAsync((void*)b.lam, lf.data(), Kp * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync((void*)b.tau, tf.data(), Kp * 4, hipMemcpyHostToDevice, s));
+  const double mu = ctx->opt.mu > 0 ? ctx->opt.mu : default_mu(ctx, y);
+  std::vector<float> ge(ng);
+  std::vector<double> eta(ctx->G);
+  for (int q = 0; q < ctx->G; ++q) eta[q] = (1.0 + ctx->opt.eta_margin) * mu * ctx->Lambda[q];
+  for (int64_t q = 0; q < ng; ++q) ge[q] = (float)eta[ctx->gblock_h[q]];
+  HIPCHK(hipMemcpyAsync((void*)b.geta, ge.data(), ng * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(b.beta, 0, (size_t)Kp * g.p_pad * 4, s));
+  HIPCHK(launch_batch_zero(g, b, Kp, s));
+  HIPCHK(hipStreamSynchronize(s));
+  ctx->have_state = false;   // the single right-hand-side state is not the batch's
+
+  const double sigma = mu / (ctx->G + 1.0);
+  const int smax = 16, min_per = 4;
+  std::vector<double> best_dual(K, -INFINITY), primal(K, INFINITY), rel(K, INFINITY);
+  std::vector<char> done(K, 0);
+  int64_t it = 0, certs = 0;
+  int ndone = 0;
+  // the certificate of right-hand side k reuses the single right-hand-side machinery
+  auto certify = [&](int k) -> pqr_status {
+    const float* bk = b.beta + (size_t)k * g.p_pad;
+    const float* tk = b.theta + (size_t)k * g.n_pad;
+    double b0 = 0.0;
+    HIPCHK(hipMemcpyAsync(&b0, b.beta0 + k, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    Ctl c;
+    std::memset(&c, 0, sizeof(c));
+    c.beta0 = b0;
+    HIPCHK(hipMemcpyAsync(ctx->ctl_kkt, &c, sizeof(Ctl), hipMemcpyHostToDevice, s));
+    IterBufs<float> v = bufs<float>(ctx);
+    v.beta = const_cast<float*>(bk);
+    v.ctl = ctx->ctl_kkt;
+    HIPCHK(launch_active_list<float>(g, v, s));
+    HIPCHK(launch_scale(ctx->w_d, lambdas[k], g.p_pad, ctx->clam_d, s));
+    Cert cert{};
+    TRY(certify_point<float>(ctx, taus[k], tk, bk, ctx->ctl_kkt, ctx->list, &cert));
+    ++certs;
+    best_dual[k] = std::max(best_dual[k], cert.dual);
+    primal[k] = cert.primal;
+    rel[k] = (primal[k] - best_dual[k]) / std::max(std::fabs(primal[k]), 1e-300);
+    if (rel[k] <= ctx->opt.tol_gap && !done[k]) { done[k] = 1; ++ndone; }
+    return PQR_OK;
+  };
+  while (ndone < K && it < ctx->opt.max_iter) {
+    const int64_t chunk = std::min<int64_t>(ctx->opt.cert_every, ctx->opt.max_iter - it);
+    for (int64_t q = 0; q < chunk; ++q)
+      HIPCHK(launch_batch_iteration(g, b, Kp, mu, sigma, eta[0], smax, min_per, s));
+    it += chunk;
+    HIPCHK(hipStreamSynchronize(s));
+    for (int k = 0; k < K; ++k)
+      if (!done[k]) TRY(certify(k));
+  }
+  // final certificates of every right-hand side at the returned iterate
+  for (int k = 0; k < K; ++k) TRY(certify(k));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (outs) {
+    std::vector<float> bf(g.p), vf(g.n);
+    for (int k = 0; k < K; ++k) {
+      pqr_result* o = outs + k;
+      double b0 = 0.0;
+      HIPCHK(hipMemcpyAsync(&b0, b.beta0 + k, 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(bf.data(), b.beta + (size_t)k * g.p_pad, g.p * 4, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      int64_t nnz = 0;
+      for (int64_t j = 0; j < g.p; ++j) nnz += bf[j] != 0.f;
+      if (o->beta_std) {
+        o->beta_std[0] = b0;
+        for (int64_t j = 0; j < g.p; ++j) o->beta_std[1 + j] = bf[j];
+      }
+      if (o->beta) {
+        std::vector<double> bs(g.p + 1);
+        bs[0] = b0;
+        for (int64_t j = 0; j < g.p; ++j) bs[1 + j] = bf[j];
+        HIPCHK(hipMemcpyAsync(ctx->scratch64, bs.data(), (g.p + 1) * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(launch_back_transform(ctx->scratch64, g.p, ctx->cm_d, ctx->cinv_d, b0, ctx->bt_out,
+                                     ctx->bpart64, s));
+        HIPCHK(hipMemcpyAsync(o->beta, ctx->bt_out, (g.p + 1) * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+      }
+      if (o->z || o->theta) {
+        for (int which = 0; which < 2; ++which) {
+          double* dst = which == 0 ? o->z : o->theta;
+          if (!dst) continue;
+          const float* src = (which == 0 ? b.z : b.theta) + (size_t)k * g.n_pad;
+          HIPCHK(hipMemcpyAsync(vf.data(), src, g.n * 4, hipMemcpyDeviceToHost, s));
+          HIPCHK(hipStreamSynchronize(s));
+          for (int64_t i = 0; i < g.n; ++i) dst[i] = vf[i];
+        }
+      }
+      o->iters = it;
+      o->certs = certs;
+      o->x_passes = it + certs;
+      o->nnz = nnz;
+      o->primal = primal[k];
+      o->dual = best_dual[k];
+      o->rel_gap = rel[k];
+      o->lambda_max = 0.0;
+      o->mu = mu;
+      o->seconds = secs;
+      o->sweep_ms = 0.0;
+      o->sweep_launches = 0;
+    }
+  }
+  if (ndone < K) {
+    ctx->err = "max_iter reached before every right-hand side met tol_gap";
+    return PQR_ERR_NOT_CONVERGED;
+  }
+  return PQR_OK;
+}
+
+}  // namespace
+
+extern "C" pqr_status pqr_solve_batch(pqr_ctx* ctx, const double* y, int K, const double* taus,
+                                      const double* lambdas, const double* weights,
+                                      pqr_result* outs) {
+  if (!ctx) return PQR_ERR_INVALID_ARG;
+  return batch_impl(ctx, y, K, taus, lambdas, weights, outs);
 }

@@ -149,3 +149,43 @@ hipError_t launch_colparams(const double* sum, const double* sumsq, int64_t n, i
 template <typename T>
 hipError_t launch_set_y(const double* y, int64_t n, int64_t n_pad, T* y_t, hipStream_t s);
 }  // namespace pqr
+
+namespace pqr {
+// Batched right-hand sides (kern_batch.hip).  Kp = K padded to a multiple of 16.
+struct BatchBufs {
+  int K;
+  float* beta;          // Kp x p_pad (right-hand side k in row k)
+  const float* cm;      // p_pad
+  const float* cinv;    // p_pad
+  const float* w;       // p_pad penalty weights w_j (0 on padding)
+  const float* lam;     // Kp
+  const float* tau;     // Kp
+  const float* geta;    // ngroups
+  const float* y;       // n_pad (shared)
+  float* z;             // Kp x n_pad
+  float* theta;         // Kp x n_pad
+  float* r;             // Kp x n_pad
+  int8_t* dig;          // S x Kp x n_pad digit slices of theta
+  long long* tpart;     // (n_pad/256) x Kp
+  long long* tsumq;     // Kp exact sum of the quantised theta
+  double* tsum;         // Kp sum of theta
+  double* scale;        // Kp digit scale c_k
+  double* beta0;        // Kp
+  double* norms;        // Kp x 4
+  uint32_t* mask;       // ngroups x Kp/16
+  int* list;            // ngroups
+  int* bcnt;            // kCompactBlocks
+  int* count;           // 1
+  double* partial;      // smax x Kp x n_pad
+  double* bpart;        // (n_pad/256) x Kp x 8
+};
+hipError_t launch_batch_iteration(const Geom& g, const BatchBufs& b, int Kp, double mu,
+                                  double sigma, double eta0, int smax, int min_per,
+                                  hipStream_t s);
+hipError_t launch_batch_zero(const Geom& g, const BatchBufs& b, int Kp, hipStream_t s);
+// flags, count and ordered list of the groups holding a nonzero of beta (b.beta);
+// b.ctl receives the count (beta0 untouched)
+template <typename T>
+hipError_t launch_active_list(const Geom& g, const IterBufs<T>& b, hipStream_t s);
+hipError_t launch_scale(const double* w, double a, int64_t m, double* out, hipStream_t s);
+}  // namespace pqr
