@@ -124,7 +124,8 @@ typedef struct {
 
 typedef enum {
   PQR_START_ZERO = 0,   /* beta = 0, z = y, theta = 0                           */
-  PQR_START_HOST = 1,   /* from warm->beta_std, warm->z, warm->theta (host)      */
+  PQR_START_HOST = 1,   /* from warm->beta_std, warm->z, warm->theta (host); z and
+                           theta may be NULL (derived from beta, see pqr_solve)  */
   PQR_START_DEVICE = 2  /* continue from the state the previous solve left on the device
                            (warm starts along a lambda path; same y, tau and mu) */
 } pqr_start;
@@ -143,7 +144,10 @@ pqr_status pqr_create(pqr_ctx** out, const pqr_design* X, const pqr_options* opt
  *  y        host, n doubles (copied)
  *  weights  host, p+1 doubles w_j >= 0 (w_0 ignored), or NULL for unit weights
  *  start    pqr_start; for PQR_START_HOST, warm must point to arrays of the
- *           sizes above (beta_std, z, theta)
+ *           sizes above (beta_std, z, theta).  warm->z may be NULL: then
+ *           z = y - X~beta - beta0 (the residual of beta, so r = 0); warm->theta
+ *           may be NULL: then theta_i = (tau - 1{z_i < 0}) / n, centred so
+ *           that sum(theta) = 0 (a subgradient of the check loss at z)
  *  out      results; see pqr_result.  On PQR_ERR_NOT_CONVERGED out still holds
  *           the last iterate and its certificate. */
 pqr_status pqr_solve(pqr_ctx* ctx, const double* y, double tau, double lambda,
@@ -196,6 +200,68 @@ pqr_status pqr_iterate(pqr_ctx* ctx, const double* y, double tau, double lambda,
  * new pqr_solve afterwards). */
 pqr_status pqr_solve_batch(pqr_ctx* ctx, const double* y, int K, const double* taus,
                            const double* lambdas, const double* weights, pqr_result* outs);
+
+/* pqr_kkt plus every column's dual value: v (host, p doubles) receives
+ * x~_j^T theta' for the projected theta' of the certificate. */
+pqr_status pqr_kkt_columns(pqr_ctx* ctx, const double* y, double tau, double lambda,
+                           const double* weights, const double* beta_std, const double* theta,
+                           double rep[4], double* v);
+
+/* A context over the columns cols[0..ncols) (host, 0-based, in increasing order)
+ * of parent: the design store and the column statistics are copied from the
+ * parent on the device (the standardization is the parent's), blocks and step
+ * sizes are set up for the subset.  opt NULL = the parent's options.  Independent
+ * of the parent afterwards. */
+pqr_status pqr_create_subset(pqr_ctx** out, pqr_ctx* parent, const int64_t* cols,
+                             int64_t ncols, const pqr_options* opt);
+
+/* ---- learned warm start: the per-feature scoring network ------------------
+ * Network 4 -> 64 -> 64 -> 2 with SiLU activations; 4610 FP32 parameters in the
+ * order W1[64][4], b1[64], W2[64][64], b2[64], W3[2][64], b3[2], used as BF16
+ * (round to nearest even) in every pass, FP32 activations and accumulations.
+ * Features of column j (pqr_features): sqrt(n) S_j / sqrt(tau (1 - tau)) with
+ * S_j the null-fit score of pqr_lambda_max, m_j / 2, tau, log(lambda/lambda_max).
+ * Outputs: o0 = proposed beta~_j / sd(y), o1 = logit of beta~_j != 0.
+ * All buffers below are device pointers; stream is a hipStream_t (NULL = default). */
+int64_t pqr_mlp_param_count(void);
+/* feats: device, p x 4 floats (row j = column j); also returns lambda_max */
+pqr_status pqr_features(pqr_ctx* ctx, const double* y, double tau, double lambda,
+                        const double* weights, float* feats, double* lambda_max);
+pqr_status pqr_mlp_forward(const float* params, const float* feats, int64_t B, float* out,
+                           void* stream);
+/* Loss (mean over the B rows of w_reg (o0 - t)^2 + w_pos a softplus(-o1)
+ * + (1 - a) softplus(o1)) and its gradient; workspace of pqr_mlp_workspace_bytes(B). */
+int64_t pqr_mlp_workspace_bytes(int64_t B);
+pqr_status pqr_mlp_grad(const float* params, const float* feats, const float* target,
+                        const float* active, int64_t B, double w_reg, double w_pos,
+                        void* workspace, float* grad, float* loss, void* stream);
+/* One Adam step (step >= 1 counts from 1) on the 4610 parameters. */
+pqr_status pqr_mlp_adam(float* params, const float* grad, float* m, float* v, int step,
+                        double lr, double beta1, double beta2, double eps, void* stream);
+
+typedef struct {
+  int rounds;               /* reduced solves run                                   */
+  int fallback;             /* 1 if the plain zero-start solve produced the answer */
+  int64_t active_initial;   /* columns proposed by the network                      */
+  int64_t active_final;     /* columns of the last reduced problem                  */
+  int64_t reduced_iters;    /* iterations spent in reduced solves                   */
+  double seconds_proposal, seconds_reduced, seconds_check;   /* cumulative          */
+} pqr_learned_report;
+
+/* Learned warm start: the network (params, device) proposes coefficients and an
+ * active set A = {j : o1_j > threshold} plus the 32 columns with the largest o1;
+ * FS-QRPPA solves the problem restricted to
+ * A (to tol_gap/4) from that proposal (beta_0 = the tau-quantile of y, z = y -
+ * beta_0, theta = the null-fit dual); the FP64 certificate on the full design then
+ * judges it.  If its gap exceeds tol_gap, the columns outside A whose
+ * |x~_j^T theta'| exceeds lambda_j (1 + 1e-6) join A, or, when there are none, the
+ * reduced solve is repeated 4x tighter, from the previous solution (at most
+ * max_rounds reduced solves).  If no round passes, the plain FS-QRPPA solve from a
+ * zero start on the full design gives the answer (rep->fallback = 1).  The
+ * reported rel_gap is always the full design's certificate. */
+pqr_status pqr_solve_learned(pqr_ctx* ctx, const double* y, double tau, double lambda,
+                             const double* weights, const float* params, double threshold,
+                             int max_rounds, pqr_result* out, pqr_learned_report* rep);
 
 void pqr_destroy(pqr_ctx* ctx);
 const char* pqr_last_error(const pqr_ctx* ctx);

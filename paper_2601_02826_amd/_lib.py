@@ -47,8 +47,17 @@ class pqr_result(ctypes.Structure):
 
 
 SYMBOLS = ["pqr_default_options", "pqr_create", "pqr_solve", "pqr_kkt", "pqr_lambda_max",
-           "pqr_blocks", "pqr_iterate", "pqr_solve_batch", "pqr_destroy", "pqr_last_error",
+           "pqr_blocks", "pqr_iterate", "pqr_solve_batch", "pqr_kkt_columns", "pqr_create_subset",
+           "pqr_mlp_param_count", "pqr_features", "pqr_mlp_forward", "pqr_mlp_workspace_bytes",
+           "pqr_mlp_grad", "pqr_mlp_adam", "pqr_solve_learned", "pqr_destroy", "pqr_last_error",
            "pqr_status_string"]
+
+
+class pqr_learned_report(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int), ("fallback", ctypes.c_int),
+                ("active_initial", ctypes.c_int64), ("active_final", ctypes.c_int64),
+                ("reduced_iters", ctypes.c_int64), ("seconds_proposal", ctypes.c_double),
+                ("seconds_reduced", ctypes.c_double), ("seconds_check", ctypes.c_double)]
 
 _lib = None
 
@@ -80,6 +89,27 @@ def load():
     lib.pqr_iterate.restype = ci
     lib.pqr_solve_batch.argtypes = [vp, _c_dp, ci, _c_dp, _c_dp, _c_dp, ctypes.POINTER(pqr_result)]
     lib.pqr_solve_batch.restype = ci
+    _c_fp = ctypes.c_void_p
+    lib.pqr_kkt_columns.argtypes = [vp, _c_dp, dbl, dbl, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp]
+    lib.pqr_kkt_columns.restype = ci
+    lib.pqr_create_subset.argtypes = [ctypes.POINTER(vp), vp, ctypes.POINTER(i64), i64,
+                                      ctypes.POINTER(pqr_options)]
+    lib.pqr_create_subset.restype = ci
+    lib.pqr_mlp_param_count.argtypes = []
+    lib.pqr_mlp_param_count.restype = i64
+    lib.pqr_features.argtypes = [vp, _c_dp, dbl, dbl, _c_dp, _c_fp, _c_dp]
+    lib.pqr_features.restype = ci
+    lib.pqr_mlp_forward.argtypes = [_c_fp, _c_fp, i64, _c_fp, vp]
+    lib.pqr_mlp_forward.restype = ci
+    lib.pqr_mlp_workspace_bytes.argtypes = [i64]
+    lib.pqr_mlp_workspace_bytes.restype = i64
+    lib.pqr_mlp_grad.argtypes = [_c_fp, _c_fp, _c_fp, _c_fp, i64, dbl, dbl, _c_fp, _c_fp, _c_fp, vp]
+    lib.pqr_mlp_grad.restype = ci
+    lib.pqr_mlp_adam.argtypes = [_c_fp, _c_fp, _c_fp, _c_fp, ci, dbl, dbl, dbl, dbl, vp]
+    lib.pqr_mlp_adam.restype = ci
+    lib.pqr_solve_learned.argtypes = [vp, _c_dp, dbl, dbl, _c_dp, _c_fp, dbl, ci,
+                                      ctypes.POINTER(pqr_result), ctypes.POINTER(pqr_learned_report)]
+    lib.pqr_solve_learned.restype = ci
     lib.pqr_destroy.argtypes = [vp]
     lib.pqr_destroy.restype = None
     lib.pqr_last_error.argtypes = [vp]
@@ -197,7 +227,8 @@ class Context:
         out = pqr_result(beta=_dptr(beta), beta_std=_dptr(beta_std), z=_dptr(z), theta=_dptr(theta))
         wr = None
         if warm is not None:
-            wb, wz, wt = _f64(warm["beta_std"], self.p + 1), _f64(warm["z"], self.n), _f64(warm["theta"], self.n)
+            wb = _f64(warm["beta_std"], self.p + 1)
+            wz, wt = _f64(warm.get("z"), self.n), _f64(warm.get("theta"), self.n)
             wr = pqr_result(beta_std=_dptr(wb), z=_dptr(wz), theta=_dptr(wt))
             start = "host"
         st = self._lib.pqr_solve(self._h, _dptr(y), float(tau), float(lam), _dptr(w), START[start],
@@ -237,6 +268,62 @@ class Context:
                               mu=o.mu, seconds=o.seconds, status=st))
         return res
 
+    def kkt_columns(self, y, tau, lam, beta_std, theta, weights=None):
+        rep = np.zeros(4)
+        v = np.zeros(self.p)
+        self._check(self._lib.pqr_kkt_columns(self._h, _dptr(_f64(y, self.n)), float(tau), float(lam),
+                                              _dptr(_f64(weights, self.p + 1)),
+                                              _dptr(_f64(beta_std, self.p + 1)),
+                                              _dptr(_f64(theta, self.n)), _dptr(rep), _dptr(v)))
+        return dict(primal=rep[0], dual=rep[1], rel_gap=rep[2], max_ratio=rep[3], v=v)
+
+    def subset(self, cols, **options):
+        """pqr_create_subset: a new Context over the listed columns of this one."""
+        cols = np.ascontiguousarray(cols, dtype=np.int64)
+        o = pqr_options.from_buffer_copy(self.options)
+        for k, val in options.items():
+            if k == "iter_prec":
+                val = ITER[val] if isinstance(val, str) else int(val)
+            setattr(o, k, val)
+        h = ctypes.c_void_p()
+        st = self._lib.pqr_create_subset(ctypes.byref(h), self._h,
+                                         cols.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                         len(cols), ctypes.byref(o))
+        if st != PQR_OK:
+            msg = self._lib.pqr_last_error(h).decode() if h.value else "pqr_create_subset failed"
+            self._lib.pqr_destroy(h)
+            raise PQRError(st, msg)
+        sub = Context.__new__(Context)
+        sub._lib, sub._h, sub.n, sub.p, sub._keep, sub.options = self._lib, h, self.n, len(cols), self, o
+        return sub
+
+    def features(self, y, tau, lam, feats_ptr, weights=None):
+        """pqr_features into a device buffer of p x 4 floats; returns lambda_max."""
+        lm = np.zeros(1)
+        self._check(self._lib.pqr_features(self._h, _dptr(_f64(y, self.n)), float(tau), float(lam),
+                                           _dptr(_f64(weights, self.p + 1)),
+                                           ctypes.c_void_p(int(feats_ptr)), _dptr(lm)))
+        return lm[0]
+
+    def solve_learned(self, y, tau, lam, params_ptr, threshold=0.0, max_rounds=4, weights=None):
+        beta = np.zeros(self.p + 1)
+        beta_std = np.zeros(self.p + 1)
+        z = np.zeros(self.n)
+        theta = np.zeros(self.n)
+        out = pqr_result(beta=_dptr(beta), beta_std=_dptr(beta_std), z=_dptr(z), theta=_dptr(theta))
+        rep = pqr_learned_report()
+        st = self._lib.pqr_solve_learned(self._h, _dptr(_f64(y, self.n)), float(tau), float(lam),
+                                         _dptr(_f64(weights, self.p + 1)),
+                                         ctypes.c_void_p(int(params_ptr)), float(threshold),
+                                         int(max_rounds), ctypes.byref(out), ctypes.byref(rep))
+        self._check(st, (PQR_OK, PQR_ERR_NOT_CONVERGED))
+        return Result(beta=beta, beta_std=beta_std, z=z, theta=theta, iters=out.iters, nnz=out.nnz,
+                      primal=out.primal, dual=out.dual, rel_gap=out.rel_gap,
+                      lambda_max=out.lambda_max, seconds=out.seconds, status=st,
+                      rounds=rep.rounds, fallback=rep.fallback, active_initial=rep.active_initial,
+                      active_final=rep.active_final, reduced_iters=rep.reduced_iters,
+                      seconds_proposal=rep.seconds_proposal)
+
     def kkt(self, y, tau, lam, beta_std, theta, weights=None):
         rep = np.zeros(4)
         self._check(self._lib.pqr_kkt(self._h, _dptr(_f64(y, self.n)), float(tau), float(lam),
@@ -269,3 +356,44 @@ class Context:
                                           _dptr(_f64(eta)), int(iters), _dptr(b), _dptr(zz),
                                           _dptr(tt)))
         return b, zz, tt
+
+
+# ---- the scoring network: free functions over device buffers (torch tensors) ----
+def _ptr(t):
+    return ctypes.c_void_p(int(t.data_ptr()))
+
+
+def mlp_param_count():
+    return int(load().pqr_mlp_param_count())
+
+
+def mlp_forward(params, feats, out, stream=None):
+    lib = load()
+    B = feats.shape[0]
+    st = lib.pqr_mlp_forward(_ptr(params), _ptr(feats), B, _ptr(out),
+                             stream if stream is not None else _current_stream())
+    if st != PQR_OK:
+        raise PQRError(st, "pqr_mlp_forward failed")
+
+
+def mlp_workspace_bytes(B):
+    return int(load().pqr_mlp_workspace_bytes(int(B)))
+
+
+def mlp_grad(params, feats, target, active, workspace, grad, loss, w_reg=1.0, w_pos=1.0,
+             stream=None):
+    lib = load()
+    st = lib.pqr_mlp_grad(_ptr(params), _ptr(feats), _ptr(target), _ptr(active), feats.shape[0],
+                          float(w_reg), float(w_pos), _ptr(workspace), _ptr(grad), _ptr(loss),
+                          stream if stream is not None else _current_stream())
+    if st != PQR_OK:
+        raise PQRError(st, "pqr_mlp_grad failed")
+
+
+def mlp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    lib = load()
+    st = lib.pqr_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr),
+                          float(beta1), float(beta2), float(eps),
+                          stream if stream is not None else _current_stream())
+    if st != PQR_OK:
+        raise PQRError(st, "pqr_mlp_adam failed")

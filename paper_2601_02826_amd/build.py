@@ -18,7 +18,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]
-SOURCES = ["kern_iter.hip", "kern_cert.hip", "kern_setup.hip", "kern_batch.hip", "pqr_api.cpp"]
+SOURCES = ["kern_iter.hip", "kern_cert.hip", "kern_setup.hip", "kern_batch.hip", "kern_mlp.hip",
+           "pqr_api.cpp"]
 
 
 def _compile(src):

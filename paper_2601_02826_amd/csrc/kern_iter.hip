@@ -296,7 +296,9 @@ __global__ __launch_bounds__(256) void k_init_r(IterBufs<T> b, IterParams ip, in
   if (i < n) {
     double s = b.ctl->beta0;
     for (int k = 0; k < seff; ++k) s += b.partial[(int64_t)k * n_pad + i];
+    if (ip.fit & 1) b.z[i] = (T)((double)b.y[i] - s);
     b.r[i] = (T)(s + (double)b.z[i] - (double)b.y[i]);
+    if (ip.fit & 2) b.theta[i] = (T)((ip.tau - ((double)b.z[i] < 0.0 ? 1.0 : 0.0)) / (double)n);
     q[6] = (double)b.theta[i];
   }
   block_sum<256, 8, double>(q, red);
@@ -318,6 +320,19 @@ __global__ __launch_bounds__(256) void k_init_r(IterBufs<T> b, IterParams ip, in
     b.ctl->delta_prev = 0;
     b.ctl->n_increase = 0;
   }
+}
+
+// theta_i -= sum(theta) / n on the n real rows (after k_init_r with ip.fit bit 1).
+template <typename T>
+__global__ __launch_bounds__(256) void k_center_theta(IterBufs<T> b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const double shift = b.ctl->sum_theta / (double)n;
+  if (i < n) b.theta[i] = (T)((double)b.theta[i] - shift);
+}
+
+template <typename T>
+__global__ void k_zero_sum_theta(IterBufs<T> b) {
+  if (threadIdx.x == 0) b.ctl->sum_theta = 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -346,6 +361,11 @@ static void prepare_fmt(const Geom& g, const IterBufs<T>& b, const IterParams& i
                      dim3(256), 0, s, g, b, ip.smax, ip.min_per);
   hipLaunchKernelGGL((k_init_r<T>), dim3((unsigned)(g.n_pad / 256)), dim3(256), 0, s, b, ip, g.n,
                      g.n_pad);
+  if (ip.fit & 2) {
+    hipLaunchKernelGGL((k_center_theta<T>), dim3((unsigned)(g.n_pad / 256)), dim3(256), 0, s, b,
+                       g.n);
+    hipLaunchKernelGGL((k_zero_sum_theta<T>), dim3(1), dim3(64), 0, s, b);
+  }
 }
 
 #define PQR_DISPATCH(FN, ...)                                                       \

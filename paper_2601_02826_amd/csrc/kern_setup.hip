@@ -499,3 +499,45 @@ template hipError_t launch_set_y<float>(const double*, int64_t, int64_t, float*,
 template hipError_t launch_set_y<double>(const double*, int64_t, int64_t, double*, hipStream_t);
 
 }  // namespace pqr
+
+namespace pqr {
+
+// dst column c <- src column cols[c], segment by segment (same geometry of rows);
+// padding columns of dst (c >= ncols) are zero.
+__global__ __launch_bounds__(256) void k_gather_cols(Geom src, const int64_t* __restrict__ cols,
+                                                     int64_t ncols, Geom dst, uint8_t* dbase) {
+  const int64_t per = src.seg_bytes / 16;   // uint4 per segment
+  const int64_t total = dst.p_pad * dst.nchunks() * per;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * 256) {
+    const int64_t c = t / (dst.nchunks() * per);
+    const int64_t rem = t - c * dst.nchunks() * per;
+    const int64_t ch = rem / per, q = rem - ch * per;
+    uint4 v = {0u, 0u, 0u, 0u};
+    if (c < ncols) v = reinterpret_cast<const uint4*>(src.seg(cols[c], ch))[q];
+    uint8_t* d = dbase + (dst.seg(c, ch) - dst.X);
+    reinterpret_cast<uint4*>(d)[q] = v;
+  }
+}
+
+hipError_t launch_gather_columns(const Geom& src, const int64_t* cols, int64_t ncols,
+                                 const Geom& dst, uint8_t* dst_base, hipStream_t s) {
+  if (src.seg_bytes % 16 || src.seg_bytes != dst.seg_bytes || src.n_pad != dst.n_pad)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gather_cols, dim3(4096), dim3(256), 0, s, src, cols, ncols, dst, dst_base);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_gather_f64(const double* src, const int64_t* cols,
+                                                    int64_t ncols, int64_t npad, double* dst) {
+  for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < npad; c += (int64_t)gridDim.x * 256)
+    dst[c] = c < ncols ? src[cols[c]] : 0.0;
+}
+
+hipError_t launch_gather_f64(const double* src, const int64_t* cols, int64_t ncols, int64_t npad,
+                             double* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_f64, dim3(256), dim3(256), 0, s, src, cols, ncols, npad, dst);
+  return hipGetLastError();
+}
+
+}  // namespace pqr

@@ -62,6 +62,8 @@ struct pqr_ctx {
   BatchBufs bb{};
   double* w_d = nullptr;            // p_pad penalty weights in FP64 (batched certificates)
   float* yb = nullptr;              // n_pad y in FP32 (batched iterations)
+  float* feats = nullptr;           // p_pad x 4 features of the scoring network
+  float* mlp_out = nullptr;         // p_pad x 2 network outputs
 };
 
 namespace {
@@ -217,10 +219,10 @@ extern "C" void pqr_destroy(pqr_ctx* ctx) {
   delete ctx;
 }
 
-static pqr_status create_impl(pqr_ctx* ctx, const pqr_design* X) {
-  const int64_t n = X->n, p = X->p;
+// Geometry of a store of p columns with n rows in format fmt.
+static void set_geometry(pqr_ctx* ctx, int fmt, int64_t n, int64_t p) {
   Geom& g = ctx->g;
-  g.fmt = X->store_fmt;
+  g.fmt = fmt;
   g.rpl = (g.fmt == B2 || n >= 8192) ? 16 : 4;
   if (ctx->opt.rows_per_lane == 16) g.rpl = 16;
   else if (ctx->opt.rows_per_lane == 4 && g.fmt != B2) g.rpl = 4;
@@ -229,30 +231,75 @@ static pqr_status create_impl(pqr_ctx* ctx, const pqr_design* X) {
   g.p = p;
   g.p_pad = round_up(p, kGroup);
   g.seg_bytes = fmt_col_bytes(g.fmt, (int64_t)kWave * g.rpl);
-  ctx->standardize = X->standardize ? 1 : 0;
-  hipStream_t s = ctx->s;
-  const int64_t ng = g.ngroups();
-  if (g.n_pad / 256 + 1024 > (int64_t)1 << 22) {
-    ctx->err = "n too large";
-    return PQR_ERR_UNSUPPORTED;
-  }
+}
 
-  TRY(dalloc(ctx, &ctx->X, (size_t)g.store_bytes()));
-  g.X = ctx->X;
-  HIPCHK(launch_encode(X->data, X->src_fmt, X->ld, g, ctx->X, s));
-
-  double *sum, *sumsq;
-  TRY(dalloc(ctx, &sum, g.p_pad * 8));
-  TRY(dalloc(ctx, &sumsq, g.p_pad * 8));
+static pqr_status alloc_colparams(pqr_ctx* ctx) {
+  const Geom& g = ctx->g;
   TRY(dalloc(ctx, &ctx->cm_d, g.p_pad * 8));
   TRY(dalloc(ctx, &ctx->cinv_d, g.p_pad * 8));
   TRY(dalloc(ctx, &ctx->sd_d, g.p_pad * 8));
   TRY(dalloc(ctx, &ctx->cm_f, g.p_pad * 4));
   TRY(dalloc(ctx, &ctx->cinv_f, g.p_pad * 4));
+  return PQR_OK;
+}
+
+static pqr_status create_rest(pqr_ctx* ctx);
+
+static pqr_status create_impl(pqr_ctx* ctx, const pqr_design* X) {
+  const int64_t n = X->n, p = X->p;
+  set_geometry(ctx, X->store_fmt, n, p);
+  Geom& g = ctx->g;
+  ctx->standardize = X->standardize ? 1 : 0;
+  hipStream_t s = ctx->s;
+  if (g.n_pad / 256 + 1024 > (int64_t)1 << 22) {
+    ctx->err = "n too large";
+    return PQR_ERR_UNSUPPORTED;
+  }
+  TRY(dalloc(ctx, &ctx->X, (size_t)g.store_bytes()));
+  g.X = ctx->X;
+  HIPCHK(launch_encode(X->data, X->src_fmt, X->ld, g, ctx->X, s));
+  double *sum, *sumsq;
+  TRY(dalloc(ctx, &sum, g.p_pad * 8));
+  TRY(dalloc(ctx, &sumsq, g.p_pad * 8));
+  TRY(alloc_colparams(ctx));
   HIPCHK(launch_colstats(g, sum, sumsq, s));
   HIPCHK(launch_colparams(sum, sumsq, n, p, g.p_pad, ctx->standardize, ctx->cm_d, ctx->cinv_d,
                           ctx->sd_d, ctx->cm_f, ctx->cinv_f, s));
+  return create_rest(ctx);
+}
 
+// A context over a subset of the parent's columns: the store and the column
+// statistics are gathered from the parent (so the standardization is the
+// parent's), then blocks and step sizes are set up for the subset.
+static pqr_status create_subset_impl(pqr_ctx* ctx, const pqr_ctx* parent, const int64_t* cols,
+                                     int64_t ncols) {
+  const Geom& pg = parent->g;
+  ctx->opt.rows_per_lane = pg.rpl;
+  set_geometry(ctx, pg.fmt, pg.n, ncols);
+  Geom& g = ctx->g;
+  ctx->standardize = parent->standardize;
+  hipStream_t s = ctx->s;
+  int64_t* cols_d;
+  TRY(dalloc(ctx, &cols_d, ncols * 8));
+  HIPCHK(hipMemcpyAsync(cols_d, cols, ncols * 8, hipMemcpyHostToDevice, s));
+  TRY(dalloc(ctx, &ctx->X, (size_t)g.store_bytes()));
+  g.X = ctx->X;
+  HIPCHK(launch_gather_columns(pg, cols_d, ncols, g, ctx->X, s));
+  TRY(alloc_colparams(ctx));
+  HIPCHK(launch_gather_f64(parent->cm_d, cols_d, ncols, g.p_pad, ctx->cm_d, s));
+  HIPCHK(launch_gather_f64(parent->cinv_d, cols_d, ncols, g.p_pad, ctx->cinv_d, s));
+  HIPCHK(launch_gather_f64(parent->sd_d, cols_d, ncols, g.p_pad, ctx->sd_d, s));
+  HIPCHK(launch_from_double<float>(ctx->cm_d, g.p_pad, ctx->cm_f, s));
+  HIPCHK(launch_from_double<float>(ctx->cinv_d, g.p_pad, ctx->cinv_f, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return create_rest(ctx);
+}
+
+static pqr_status create_rest(pqr_ctx* ctx) {
+  Geom& g = ctx->g;
+  const int64_t n = g.n, p = g.p;
+  hipStream_t s = ctx->s;
+  const int64_t ng = g.ngroups();
   // blocks: contiguous near-equal runs of 16-column groups; the intercept is
   // either a block of its own (block 0) or the first column of block 0
   int Gf = ctx->opt.G > 0 ? ctx->opt.G : 48;
@@ -501,6 +548,7 @@ pqr_status init_state(pqr_ctx* ctx, int start, const double* beta_std, const dou
   hipStream_t s = ctx->s;
   Ctl c;
   std::memset(&c, 0, sizeof(c));
+  int fit = 0;
   if (start == PQR_START_DEVICE) {
     HIPCHK(hipMemcpyAsync(&c, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -514,24 +562,29 @@ pqr_status init_state(pqr_ctx* ctx, int start, const double* beta_std, const dou
     HIPCHK(hipMemcpyAsync(ctx->scratch64, tmp.data(), g.p_pad * 8, hipMemcpyHostToDevice, s));
     HIPCHK(launch_from_double<T>(ctx->scratch64, g.p_pad, (T*)ctx->beta, s));
     HIPCHK(hipStreamSynchronize(s));
+    // a null z (theta) is derived from beta on the device: z = y - X~beta - beta0,
+    // theta_i = (tau - 1{z_i < 0}) / n centred to sum zero
     std::fill(tmp.begin(), tmp.end(), 0.0);
-    std::memcpy(tmp.data(), zh, g.n * 8);
+    if (zh) std::memcpy(tmp.data(), zh, g.n * 8);
     HIPCHK(hipMemcpyAsync(ctx->scratch64, tmp.data(), g.n_pad * 8, hipMemcpyHostToDevice, s));
     HIPCHK(launch_from_double<T>(ctx->scratch64, g.n_pad, (T*)ctx->z, s));
     HIPCHK(hipStreamSynchronize(s));
     std::fill(tmp.begin(), tmp.end(), 0.0);
-    std::memcpy(tmp.data(), th, g.n * 8);
+    if (th) std::memcpy(tmp.data(), th, g.n * 8);
     HIPCHK(hipMemcpyAsync(ctx->scratch64, tmp.data(), g.n_pad * 8, hipMemcpyHostToDevice, s));
     HIPCHK(launch_from_double<T>(ctx->scratch64, g.n_pad, (T*)ctx->theta, s));
     HIPCHK(hipStreamSynchronize(s));
     c.beta0 = beta_std[0];
+    fit = (zh ? 0 : 1) | (th ? 0 : 2);
   } else {
     HIPCHK(hipMemsetAsync(ctx->beta, 0, g.p_pad * sizeof(T), s));
     HIPCHK(hipMemcpyAsync(ctx->z, ctx->y_t, g.n_pad * sizeof(T), hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemsetAsync(ctx->theta, 0, g.n_pad * sizeof(T), s));
   }
   HIPCHK(hipMemcpyAsync(ctx->ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, s));
-  HIPCHK(launch_prepare_state<T>(g, bufs<T>(ctx), ip, s));
+  IterParams ipf = ip;
+  ipf.fit = fit;
+  HIPCHK(launch_prepare_state<T>(g, bufs<T>(ctx), ipf, s));
   HIPCHK(hipStreamSynchronize(s));
   return PQR_OK;
 }
@@ -645,8 +698,8 @@ pqr_status solve_impl(pqr_ctx* ctx, const double* y, double tau, double lambda,
                       const double* weights, int start, const pqr_result* warm, pqr_result* out) {
   const auto t0 = std::chrono::steady_clock::now();
   TRY(validate_problem(ctx, y, tau, lambda, weights));
-  if (start == PQR_START_HOST && (!warm || !warm->beta_std || !warm->z || !warm->theta)) {
-    ctx->err = "PQR_START_HOST needs warm->beta_std, warm->z and warm->theta";
+  if (start == PQR_START_HOST && (!warm || !warm->beta_std)) {
+    ctx->err = "PQR_START_HOST needs warm->beta_std";
     return PQR_ERR_INVALID_ARG;
   }
   if (start == PQR_START_DEVICE && !ctx->have_state) {
@@ -818,9 +871,9 @@ extern "C" pqr_status pqr_iterate(pqr_ctx* ctx, const double* y, double tau, dou
   return iterate_impl<float>(ctx, y, tau, lambda, weights, mu, eta, iters, beta_std, z, theta);
 }
 
-extern "C" pqr_status pqr_kkt(pqr_ctx* ctx, const double* y, double tau, double lambda,
-                              const double* weights, const double* beta_std, const double* theta,
-                              double rep[4]) {
+static pqr_status kkt_impl(pqr_ctx* ctx, const double* y, double tau, double lambda,
+                           const double* weights, const double* beta_std, const double* theta,
+                           double rep[4], double* v_out) {
   if (!ctx) return PQR_ERR_INVALID_ARG;
   TRY(validate_problem(ctx, y, tau, lambda, weights));
   if (!beta_std || !theta || !rep) {
@@ -850,8 +903,9 @@ extern "C" pqr_status pqr_kkt(pqr_ctx* ctx, const double* y, double tau, double 
   HIPCHK(launch_project<double>(ctx->scratch64, g.n, g.n_pad, tau, ctx->y_d, ctx->theta_p,
                                 ctx->out_d, s));
   HIPCHK(launch_dots64(g, ctx->theta_p, ctx->out_d + 5, ctx->cm_d, ctx->cinv_d, ctx->clam_d,
-                       nullptr, ctx->gpart, s));
+                       v_out ? ctx->v_d : nullptr, ctx->gpart, s));
   HIPCHK(launch_reduce_max(ctx->gpart, g.ngroups(), ctx->bpart64, ctx->out_d + 3, s));
+  if (v_out) HIPCHK(hipMemcpyAsync(v_out, ctx->v_d, g.p * 8, hipMemcpyDeviceToHost, s));
   CertBufs cb{};
   cb.y = ctx->y_d;
   cb.theta_p = ctx->theta_p;
@@ -875,6 +929,22 @@ extern "C" pqr_status pqr_kkt(pqr_ctx* ctx, const double* y, double tau, double 
   rep[2] = (rep[0] - rep[1]) / std::max(std::fabs(rep[0]), 1e-300);
   rep[3] = mr;
   return PQR_OK;
+}
+
+extern "C" pqr_status pqr_kkt(pqr_ctx* ctx, const double* y, double tau, double lambda,
+                              const double* weights, const double* beta_std, const double* theta,
+                              double rep[4]) {
+  return kkt_impl(ctx, y, tau, lambda, weights, beta_std, theta, rep, nullptr);
+}
+
+extern "C" pqr_status pqr_kkt_columns(pqr_ctx* ctx, const double* y, double tau, double lambda,
+                                      const double* weights, const double* beta_std,
+                                      const double* theta, double rep[4], double* v) {
+  if (!v) {
+    if (ctx) ctx->err = "pqr_kkt_columns needs v";
+    return PQR_ERR_INVALID_ARG;
+  }
+  return kkt_impl(ctx, y, tau, lambda, weights, beta_std, theta, rep, v);
 }
 
 extern "C" pqr_status pqr_lambda_max(pqr_ctx* ctx, const double* y, double tau,
@@ -1088,4 +1158,259 @@ extern "C" pqr_status pqr_solve_batch(pqr_ctx* ctx, const double* y, int K, cons
                                       pqr_result* outs) {
   if (!ctx) return PQR_ERR_INVALID_ARG;
   return batch_impl(ctx, y, K, taus, lambdas, weights, outs);
+}
+
+// ---------------------------------------------------------------------------
+// Column subsets, the scoring network and the learned warm start
+// ---------------------------------------------------------------------------
+extern "C" pqr_status pqr_create_subset(pqr_ctx** out, pqr_ctx* parent, const int64_t* cols,
+                                        int64_t ncols, const pqr_options* opt) {
+  if (!out) return PQR_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!parent) return PQR_ERR_INVALID_ARG;
+  pqr_ctx* ctx = new pqr_ctx();
+  ctx->opt = opt ? *opt : parent->opt;
+  if (ctx->opt.mu_scale <= 0) ctx->opt.mu_scale = parent->opt.mu_scale;
+  if (ctx->opt.eta_margin == 0 || ctx->opt.eta_margin <= -1) ctx->opt.eta_margin = 0.01;
+  if (ctx->opt.tol_gap <= 0) ctx->opt.tol_gap = parent->opt.tol_gap;
+  if (ctx->opt.cert_every <= 0) ctx->opt.cert_every = parent->opt.cert_every;
+  if (ctx->opt.max_iter <= 0) ctx->opt.max_iter = parent->opt.max_iter;
+  if (ctx->opt.iter_prec != PQR_ITER_F64) ctx->opt.iter_prec = PQR_ITER_F32;
+  ctx->s = (hipStream_t)ctx->opt.stream;
+  *out = ctx;
+  if (!cols || ncols < 1) {
+    ctx->err = "pqr_create_subset needs at least one column";
+    return PQR_ERR_INVALID_ARG;
+  }
+  for (int64_t c = 0; c < ncols; ++c)
+    if (cols[c] < 0 || cols[c] >= parent->g.p) {
+      ctx->err = "column index out of range";
+      return PQR_ERR_INVALID_ARG;
+    }
+  return create_subset_impl(ctx, parent, cols, ncols);
+}
+
+extern "C" pqr_status pqr_features(pqr_ctx* ctx, const double* y, double tau, double lambda,
+                                   const double* weights, float* feats, double* lambda_max) {
+  if (!ctx) return PQR_ERR_INVALID_ARG;
+  TRY(validate_problem(ctx, y, tau, lambda, weights));
+  if (!feats) { ctx->err = "feats is NULL"; return PQR_ERR_INVALID_ARG; }
+  double lm = 0.0;
+  if (ctx->opt.iter_prec == PQR_ITER_F64) TRY(upload_problem<double>(ctx, y, tau, lambda, weights, &lm, nullptr));
+  else TRY(upload_problem<float>(ctx, y, tau, lambda, weights, &lm, nullptr));
+  const double loglam = std::log(std::max(lambda, 1e-300) / std::max(lm, 1e-300));
+  HIPCHK(launch_features(ctx->v_d, ctx->cm_d, ctx->cinv_d, ctx->g.p, (double)ctx->g.n, tau, loglam,
+                         feats, ctx->s));
+  HIPCHK(hipStreamSynchronize(ctx->s));
+  if (lambda_max) *lambda_max = lm;
+  return PQR_OK;
+}
+
+extern "C" int64_t pqr_mlp_param_count(void) { return 4610; }
+
+extern "C" int64_t pqr_mlp_workspace_bytes(int64_t B) {
+  const int64_t np = mlp_grad_partials(B < 1 ? 1 : B);
+  return np * 4610 * 4 + np * 4 + 256;
+}
+
+extern "C" pqr_status pqr_mlp_forward(const float* params, const float* feats, int64_t B, float* out,
+                                      void* stream) {
+  if (!params || !feats || !out || B < 0) return PQR_ERR_INVALID_ARG;
+  if (B == 0) return PQR_OK;
+  if (launch_mlp_forward(params, feats, B, out, (hipStream_t)stream) != hipSuccess)
+    return PQR_ERR_DEVICE;
+  return PQR_OK;
+}
+
+extern "C" pqr_status pqr_mlp_grad(const float* params, const float* feats, const float* target,
+                                   const float* active, int64_t B, double w_reg, double w_pos,
+                                   void* workspace, float* grad, float* loss, void* stream) {
+  if (!params || !feats || !target || !active || !workspace || !grad || B < 1)
+    return PQR_ERR_INVALID_ARG;
+  const int64_t np = mlp_grad_partials(B);
+  float* part = static_cast<float*>(workspace);
+  float* lpart = part + np * 4610;
+  if (launch_mlp_grad(params, feats, target, active, B, (float)w_reg, (float)w_pos, part, lpart,
+                      grad, loss, (hipStream_t)stream) != hipSuccess)
+    return PQR_ERR_DEVICE;
+  return PQR_OK;
+}
+
+extern "C" pqr_status pqr_mlp_adam(float* params, const float* grad, float* m, float* v, int step,
+                                   double lr, double beta1, double beta2, double eps, void* stream) {
+  if (!params || !grad || !m || !v || step < 1) return PQR_ERR_INVALID_ARG;
+  if (launch_adam(params, grad, m, v, 4610, (float)lr, (float)beta1, (float)beta2, (float)eps, step,
+                  (hipStream_t)stream) != hipSuccess)
+    return PQR_ERR_DEVICE;
+  return PQR_OK;
+}
+
+extern "C" pqr_status pqr_solve_learned(pqr_ctx* ctx, const double* y, double tau, double lambda,
+                                        const double* weights, const float* mlp_params,
+                                        double threshold, int max_rounds, pqr_result* out,
+                                        pqr_learned_report* rep) {
+  if (!ctx) return PQR_ERR_INVALID_ARG;
+  const auto t0 = std::chrono::steady_clock::now();
+  auto secs = [&]() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  };
+  TRY(validate_problem(ctx, y, tau, lambda, weights));
+  if (!mlp_params || max_rounds < 1) {
+    ctx->err = "pqr_solve_learned needs the network parameters and max_rounds >= 1";
+    return PQR_ERR_INVALID_ARG;
+  }
+  const Geom& g = ctx->g;
+  hipStream_t s = ctx->s;
+  pqr_learned_report r{};
+  // 1. proposal: features, network, thresholded active set
+  if (!ctx->feats) TRY(dalloc(ctx, &ctx->feats, g.p_pad * 16));
+  if (!ctx->mlp_out) TRY(dalloc(ctx, &ctx->mlp_out, g.p_pad * 8));
+  double lmax = 0.0;
+  TRY(pqr_features(ctx, y, tau, lambda, weights, ctx->feats, &lmax));
+  const double q = ctx->out_h[0];   // tau-quantile of y (null-fit intercept)
+  HIPCHK(launch_mlp_forward(mlp_params, ctx->feats, g.p, ctx->mlp_out, s));
+  std::vector<float> o(g.p * 2);
+  HIPCHK(hipMemcpyAsync(o.data(), ctx->mlp_out, g.p * 8, hipMemcpyDeviceToHost, s));
+  std::vector<double> cinv(g.p);
+  HIPCHK(hipMemcpyAsync(cinv.data(), ctx->cinv_d, g.p * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double my = 0, vy = 0;
+  for (int64_t i = 0; i < g.n; ++i) my += y[i];
+  my /= g.n;
+  for (int64_t i = 0; i < g.n; ++i) vy += (y[i] - my) * (y[i] - my);
+  const double sdy = std::sqrt(vy / g.n);
+  // A = {j : o1_j > threshold} plus the 32 columns with the largest logits, so
+  // that a cautious network still proposes a starting support
+  std::vector<int64_t> order;
+  for (int64_t j = 0; j < g.p; ++j)
+    if (cinv[j] != 0.0) order.push_back(j);
+  const size_t ktop = std::min<size_t>(32, order.size());
+  std::partial_sort(order.begin(), order.begin() + ktop, order.end(),
+                    [&](int64_t a, int64_t b) { return o[2 * a + 1] > o[2 * b + 1]; });
+  std::vector<char> pick(g.p, 0);
+  for (size_t k = 0; k < ktop; ++k) pick[order[k]] = 1;
+  std::vector<int64_t> A;
+  for (int64_t j = 0; j < g.p; ++j)
+    if (cinv[j] != 0.0 && (pick[j] || o[2 * j + 1] > threshold)) A.push_back(j);
+  r.active_initial = (int64_t)A.size();
+  r.seconds_proposal = secs();
+  std::vector<double> bfull(g.p + 1, 0.0), zbest(g.n), tbest(g.n);
+  std::vector<double> lamj(g.p);
+  for (int64_t j = 0; j < g.p; ++j) lamj[j] = lambda * (weights ? weights[1 + j] : 1.0);
+  // warm state carried between rounds (full-length beta on the solver scale); the
+  // first round derives z = y - X~beta^0 and theta from its signs on the device
+  std::vector<double> bw(g.p + 1, 0.0), zw(g.n), tw(g.n);
+  bw[0] = q;
+  for (int64_t j : A) bw[1 + j] = o[2 * j] * sdy;
+  bool ok = false;
+  double cert[4] = {0, 0, 0, 0};
+  int64_t iters = 0;
+  std::vector<double> v(g.p);
+  // With no violator outside A the full design's certificate equals the reduced
+  // one (beta is zero there and the dual scaling sees no larger ratio), so the
+  // reduced problem is solved to the target; a first round with more rounds to
+  // come stops at 10x the target, enough to expose violators cheaply.
+  const double tol = ctx->opt.tol_gap;
+  double sub_tol = max_rounds > 1 ? 10.0 * tol : tol;
+  for (int round = 0; round < max_rounds && !A.empty(); ++round) {
+    ++r.rounds;
+    pqr_ctx* sub = nullptr;
+    pqr_options so = ctx->opt;
+    so.profile = 0;
+    so.tol_gap = sub_tol;
+    so.G = (int)std::max<int64_t>(1, std::min<int64_t>(ctx->Gf, ((int64_t)A.size() + 15) / 16));
+    pqr_status st = pqr_create_subset(&sub, ctx, A.data(), (int64_t)A.size(), &so);
+    if (st != PQR_OK) {
+      ctx->err = std::string("subset: ") + (sub ? sub->err : "");
+      pqr_destroy(sub);
+      return st;
+    }
+    std::vector<double> ws(1 + A.size()), wsub;
+    ws[0] = bw[0];
+    for (size_t c = 0; c < A.size(); ++c) ws[1 + c] = bw[1 + A[c]];
+    std::vector<double> wl;
+    if (weights) {
+      wl.resize(1 + A.size());
+      wl[0] = weights[0];
+      for (size_t c = 0; c < A.size(); ++c) wl[1 + c] = weights[1 + A[c]];
+    }
+    std::vector<double> bsub(1 + A.size()), zsub(g.n), tsub(g.n);
+    pqr_result warm{};
+    warm.beta_std = ws.data();
+    warm.z = round ? zw.data() : nullptr;
+    warm.theta = round ? tw.data() : nullptr;
+    pqr_result res{};
+    res.beta_std = bsub.data();
+    res.z = zsub.data();
+    res.theta = tsub.data();
+    st = pqr_solve(sub, y, tau, lambda, weights ? wl.data() : nullptr, PQR_START_HOST, &warm, &res);
+    iters += res.iters;
+    r.reduced_iters += res.iters;
+    pqr_destroy(sub);
+    if (st != PQR_OK && st != PQR_ERR_NOT_CONVERGED) return st;
+    // embed and check on the full design: FP64 certificate and every column's dual value
+    std::fill(bfull.begin(), bfull.end(), 0.0);
+    bfull[0] = bsub[0];
+    for (size_t c = 0; c < A.size(); ++c) bfull[1 + A[c]] = bsub[1 + c];
+    TRY(pqr_kkt_columns(ctx, y, tau, lambda, weights, bfull.data(), tsub.data(), cert, v.data()));
+    bw = bfull;
+    zw = zsub;
+    tw = tsub;
+    zbest = zsub;
+    tbest = tsub;
+    std::vector<char> in(g.p, 0);
+    for (int64_t j : A) in[j] = 1;
+    if (cert[2] <= tol) { ok = true; break; }   // the full certificate decides
+    std::vector<int64_t> viol;
+    for (int64_t j = 0; j < g.p; ++j)
+      if (!in[j] && cinv[j] != 0.0 && std::fabs(v[j]) > lamj[j] * (1.0 + 1e-6)) viol.push_back(j);
+    // the support is covered: finish at the target, or tighter if it already was
+    sub_tol = sub_tol > tol ? tol : 0.25 * sub_tol;
+    if (viol.empty()) continue;
+    std::vector<int64_t> merged;
+    merged.reserve(A.size() + viol.size());
+    std::merge(A.begin(), A.end(), viol.begin(), viol.end(), std::back_inserter(merged));
+    A.swap(merged);
+  }
+  r.active_final = (int64_t)A.size();
+  r.seconds_reduced = secs();
+  pqr_status status = PQR_OK;
+  if (!ok) {
+    // fallback: plain FS-QRPPA from a zero start on the full design
+    r.fallback = 1;
+    pqr_result res{};
+    res.beta_std = bfull.data();
+    res.z = zbest.data();
+    res.theta = tbest.data();
+    status = pqr_solve(ctx, y, tau, lambda, weights, PQR_START_ZERO, nullptr, &res);
+    iters += res.iters;
+    cert[0] = res.primal;
+    cert[1] = res.dual;
+    cert[2] = res.rel_gap;
+    if (status != PQR_OK && status != PQR_ERR_NOT_CONVERGED) return status;
+  }
+  if (out) {
+    int64_t nnz = 0;
+    for (int64_t j = 0; j < g.p; ++j) nnz += bfull[1 + j] != 0.0;
+    if (out->beta_std) std::memcpy(out->beta_std, bfull.data(), (g.p + 1) * 8);
+    if (out->beta) {
+      HIPCHK(hipMemcpyAsync(ctx->scratch64, bfull.data(), (g.p + 1) * 8, hipMemcpyHostToDevice, s));
+      HIPCHK(launch_back_transform(ctx->scratch64, g.p, ctx->cm_d, ctx->cinv_d, bfull[0],
+                                   ctx->bt_out, ctx->bpart64, s));
+      HIPCHK(hipMemcpyAsync(out->beta, ctx->bt_out, (g.p + 1) * 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    if (out->z) std::memcpy(out->z, zbest.data(), g.n * 8);
+    if (out->theta) std::memcpy(out->theta, tbest.data(), g.n * 8);
+    out->iters = iters;
+    out->nnz = nnz;
+    out->primal = cert[0];
+    out->dual = cert[1];
+    out->rel_gap = cert[2];
+    out->lambda_max = lmax;
+    out->seconds = secs();
+  }
+  r.seconds_check = secs();
+  if (rep) *rep = r;
+  return status;
 }

@@ -56,6 +56,9 @@ struct IterParams {
   double tau, mu, sigma, eta0;
   int G;
   int smax, min_per;
+  // launch_prepare_state only: bit 0 sets z = y - X~beta - beta0 (so r = 0),
+  // bit 1 sets theta_i = (tau - 1{z_i < 0}) / n, centred to sum zero
+  int fit;
 };
 
 // One FS-QRPPA iteration = sweep, compact, axpy, update.  With non-null
@@ -65,7 +68,8 @@ hipError_t launch_iteration(const Geom& g, const IterBufs<T>& b, const IterParam
                             hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // Recompute the cached residual r = X~beta + beta0 + z - y and sum(theta) for a
-// given state (after a warm start); also rebuilds the active list.
+// given state (after a warm start); also rebuilds the active list.  ip.fit
+// derives z and/or theta from beta instead (see IterParams).
 template <typename T>
 hipError_t launch_prepare_state(const Geom& g, const IterBufs<T>& b, const IterParams& ip,
                                 hipStream_t s);
@@ -188,4 +192,22 @@ hipError_t launch_batch_zero(const Geom& g, const BatchBufs& b, int Kp, hipStrea
 template <typename T>
 hipError_t launch_active_list(const Geom& g, const IterBufs<T>& b, hipStream_t s);
 hipError_t launch_scale(const double* w, double a, int64_t m, double* out, hipStream_t s);
+}  // namespace pqr
+
+namespace pqr {
+// scoring network (kern_mlp.hip)
+hipError_t launch_mlp_forward(const float* P, const float* F, int64_t B, float* out, hipStream_t s);
+int mlp_grad_partials(int64_t B);
+hipError_t launch_mlp_grad(const float* P, const float* F, const float* t, const float* a,
+                           int64_t B, float w_reg, float w_pos, float* part, float* lpart,
+                           float* grad, float* loss, hipStream_t s);
+hipError_t launch_adam(float* P, const float* g, float* m, float* v, int n, float lr, float b1,
+                       float b2, float eps, int step, hipStream_t s);
+hipError_t launch_features(const double* score, const double* cm, const double* cinv, int64_t p,
+                           double n, double tau, double loglam, float* F, hipStream_t s);
+// copy the segments of the listed columns of src into dst (same format and rows)
+hipError_t launch_gather_columns(const Geom& src, const int64_t* cols, int64_t ncols,
+                                 const Geom& dst, uint8_t* dst_base, hipStream_t s);
+hipError_t launch_gather_f64(const double* src, const int64_t* cols, int64_t ncols, int64_t npad,
+                             double* dst, hipStream_t s);
 }  // namespace pqr
