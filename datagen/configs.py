@@ -9,6 +9,7 @@ Counter layout (every draw is one Philox4x32-10 call, key = (seed, tag)):
     stream 5  noise of row i           counter (i, 0, 5, 0), words 0..3
     stream 6  Gaussian entry (i, j)    counter (i, j, 6, 0), words 0 and 1
     stream 7  Gaussian-design truth    counter (j, 0, 7, 0), words 0..2
+    stream 8  grouped problem i shape  counter (i, 0, 8, 0), words 0..2
 
 A genotype entry is the sum of two Bernoulli(MAF_j) draws, x = [w0 < T_j] +
 [w1 < T_j], with the integer threshold T_j = floor(MAF_j * 2^32).  Because the
@@ -168,3 +169,22 @@ SPECS = {
     "geno_10kx500k": GenotypeSpec(n=10_000, p=500_000, n_causal=50, seed=4, tag=4,
                                   tau=0.5),
 }
+
+
+def grouped_specs(nprob=64, seed=5, tag=5, n_range=(500, 5000), p_range=(10_000, 200_000),
+                  lam_range=(0.2, 0.6), n_causal=20):
+    """Independent uneven genotype problems (stream 8 of key (seed, tag)): problem i
+    has n_i ~ U{n_range}, p_i ~ U{p_range} (inclusive, from words 0 and 1),
+    lambda_i / lambda_max,i ~ U(lam_range) (word 2) and tau_i = 0.1 (i mod 9) + 0.1;
+    its design and response come from GenotypeSpec with key (seed, tag * 1000 + i).
+    Returns a list of (GenotypeSpec, lam_frac)."""
+    w = philox4x32(np.arange(nprob, dtype=np.uint64), 0, 8, 0, seed, tag)
+    out = []
+    for i in range(nprob):
+        n = n_range[0] + int(w[0][i]) % (n_range[1] - n_range[0] + 1)
+        p = p_range[0] + int(w[1][i]) % (p_range[1] - p_range[0] + 1)
+        lf = lam_range[0] + (lam_range[1] - lam_range[0]) * float(uniform01(w[2][i:i + 1])[0])
+        tau = round(0.1 * (i % 9) + 0.1, 10)
+        out.append((GenotypeSpec(n=n, p=p, n_causal=n_causal, seed=seed, tag=tag * 1000 + i,
+                                 tau=tau, lam_frac=lf), lf))
+    return out

@@ -201,6 +201,28 @@ pqr_status pqr_iterate(pqr_ctx* ctx, const double* y, double tau, double lambda,
 pqr_status pqr_solve_batch(pqr_ctx* ctx, const double* y, int K, const double* taus,
                            const double* lambdas, const double* weights, pqr_result* outs);
 
+/* Many independent problems (X_i, y_i, tau_i, lambda_i), one per context, solved
+ * together from zero starts: every still-running problem takes one FS-QRPPA
+ * iteration (Algorithm 1, eq. fsppa_update) per round of five grouped kernel
+ * launches on ctxs[0]'s stream, each grid covering the blocks of all problems;
+ * each problem stops on its own FP64 duality-gap certificate (its own
+ * cert_every, tol_gap, max_iter) and leaves the group.
+ *  nprob        >= 1 distinct contexts; all need the same store format,
+ *               rows_per_lane and iterate precision (PQR_ERR_UNSUPPORTED otherwise)
+ *  ys           host, nprob pointers to n_i doubles
+ *  taus, lambdas host, nprob doubles each
+ *  weights      NULL, or host, nprob pointers (each NULL or p_i+1 doubles)
+ *  outs         NULL or host array of nprob pqr_result, filled as by pqr_solve;
+ *               with ctxs[0]'s profile option, sweep_ms is the summed duration of
+ *               the grouped sweep launches (all problems), the same in every out
+ *  statuses     NULL or host array of nprob statuses, one per problem
+ * Returns PQR_OK if every problem converged, else the first problem's failure
+ * (its message on that context).  Contexts must not be used concurrently. */
+pqr_status pqr_solve_grouped(int nprob, pqr_ctx* const* ctxs, const double* const* ys,
+                             const double* taus, const double* lambdas,
+                             const double* const* weights, pqr_result* outs,
+                             pqr_status* statuses);
+
 /* pqr_kkt plus every column's dual value: v (host, p doubles) receives
  * x~_j^T theta' for the projected theta' of the certificate. */
 pqr_status pqr_kkt_columns(pqr_ctx* ctx, const double* y, double tau, double lambda,

@@ -49,8 +49,8 @@ class pqr_result(ctypes.Structure):
 SYMBOLS = ["pqr_default_options", "pqr_create", "pqr_solve", "pqr_kkt", "pqr_lambda_max",
            "pqr_blocks", "pqr_iterate", "pqr_solve_batch", "pqr_kkt_columns", "pqr_create_subset",
            "pqr_mlp_param_count", "pqr_features", "pqr_mlp_forward", "pqr_mlp_workspace_bytes",
-           "pqr_mlp_grad", "pqr_mlp_adam", "pqr_solve_learned", "pqr_destroy", "pqr_last_error",
-           "pqr_status_string"]
+           "pqr_mlp_grad", "pqr_mlp_adam", "pqr_solve_learned", "pqr_solve_grouped",
+           "pqr_destroy", "pqr_last_error", "pqr_status_string"]
 
 
 class pqr_learned_report(ctypes.Structure):
@@ -110,6 +110,10 @@ def load():
     lib.pqr_solve_learned.argtypes = [vp, _c_dp, dbl, dbl, _c_dp, _c_fp, dbl, ci,
                                       ctypes.POINTER(pqr_result), ctypes.POINTER(pqr_learned_report)]
     lib.pqr_solve_learned.restype = ci
+    lib.pqr_solve_grouped.argtypes = [ci, ctypes.POINTER(vp), ctypes.POINTER(_c_dp), _c_dp, _c_dp,
+                                      ctypes.POINTER(_c_dp), ctypes.POINTER(pqr_result),
+                                      ctypes.POINTER(ci)]
+    lib.pqr_solve_grouped.restype = ci
     lib.pqr_destroy.argtypes = [vp]
     lib.pqr_destroy.restype = None
     lib.pqr_last_error.argtypes = [vp]
@@ -397,3 +401,42 @@ def mlp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8
                           stream if stream is not None else _current_stream())
     if st != PQR_OK:
         raise PQRError(st, "pqr_mlp_adam failed")
+
+
+def solve_grouped(ctxs, ys, taus, lams, weights=None, allow_not_converged=False, check=True):
+    """pqr_solve_grouped: problem i is (ctxs[i], ys[i], taus[i], lams[i]), all iterated
+    in shared launches.  Returns (results, statuses); with check, raises PQRError when
+    a problem fails (NOT_CONVERGED tolerated with allow_not_converged)."""
+    lib = load()
+    P = len(ctxs)
+    if not (len(ys) == len(taus) == len(lams) == P) or P < 1:
+        raise ValueError("ctxs, ys, taus and lams must have the same nonzero length")
+    yv = [_f64(ys[i], ctxs[i].n) for i in range(P)]
+    wv = [None] * P if weights is None else [_f64(weights[i], ctxs[i].p + 1) for i in range(P)]
+    handles = (ctypes.c_void_p * P)(*[c._h.value for c in ctxs])
+    yp = (_c_dp * P)(*[_dptr(a) for a in yv])
+    wp = None if weights is None else (_c_dp * P)(*[_dptr(a) for a in wv])
+    outs = (pqr_result * P)()
+    keep = []
+    for i, c in enumerate(ctxs):
+        arr = dict(beta=np.zeros(c.p + 1), beta_std=np.zeros(c.p + 1), z=np.zeros(c.n),
+                   theta=np.zeros(c.n))
+        keep.append(arr)
+        outs[i].beta, outs[i].beta_std = _dptr(arr["beta"]), _dptr(arr["beta_std"])
+        outs[i].z, outs[i].theta = _dptr(arr["z"]), _dptr(arr["theta"])
+    sts = (ctypes.c_int * P)()
+    st = lib.pqr_solve_grouped(P, handles, yp, _dptr(_f64(taus)), _dptr(_f64(lams)), wp, outs, sts)
+    ok = (PQR_OK, PQR_ERR_NOT_CONVERGED) if allow_not_converged else (PQR_OK,)
+    statuses = list(sts)
+    if check and st not in ok:
+        bad = next((i for i in range(P) if statuses[i] not in ok), 0)
+        raise PQRError(st, f"problem {bad}: " + lib.pqr_last_error(ctxs[bad]._h).decode())
+    res = []
+    for i in range(P):
+        o = outs[i]
+        res.append(Result(**keep[i], iters=o.iters, x_passes=o.x_passes, certs=o.certs, nnz=o.nnz,
+                          primal=o.primal, dual=o.dual, rel_gap=o.rel_gap,
+                          lambda_max=o.lambda_max, mu=o.mu, seconds=o.seconds,
+                          sweep_ms=o.sweep_ms, sweep_launches=o.sweep_launches,
+                          status=statuses[i]))
+    return res, statuses

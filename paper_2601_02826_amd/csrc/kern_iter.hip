@@ -12,6 +12,10 @@
 //   k_update   the z prox of eq. z_update, the extrapolated dual step of
 //              eq. fsppa_update, and the norms of the iteration (including
 //              the H-norm successive difference), reduced by the last block.
+//
+// Each kernel is a thin wrapper around a device body that takes its block
+// number explicitly, so that the grouped launches (many independent problems
+// per launch, one table of problem descriptors) run the same code.
 #include "pqr_kernels.h"
 
 namespace pqr {
@@ -60,9 +64,9 @@ __device__ __forceinline__ void group_dots(const Geom& g, int64_t grp, const T* 
 
 // ---------------------------------------------------------------------------
 template <int FMT, int RPL, typename T>
-__global__ __launch_bounds__(256) void k_sweep(Geom g, IterBufs<T> b) {
+__device__ __forceinline__ void sweep_body(const Geom& g, const IterBufs<T>& b, int64_t blk) {
   const int lane = threadIdx.x & 63;
-  const int64_t grp = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t grp = blk * 4 + (threadIdx.x >> 6);
   if (grp >= g.ngroups()) return;
   double acc[kGroup];
   group_dots<FMT, RPL, T>(g, grp, b.theta, acc);
@@ -92,6 +96,11 @@ __global__ __launch_bounds__(256) void k_sweep(Geom g, IterBufs<T> b) {
   }
 }
 
+template <int FMT, int RPL, typename T>
+__global__ __launch_bounds__(256) void k_sweep(Geom g, IterBufs<T> b) {
+  sweep_body<FMT, RPL, T>(g, b, blockIdx.x);
+}
+
 // Flags only (for a warm start): group has a nonzero coefficient.
 template <typename T>
 __global__ __launch_bounds__(256) void k_flags(int64_t ngroups, IterBufs<T> b) {
@@ -110,18 +119,18 @@ __global__ __launch_bounds__(256) void k_flags(int64_t ngroups, IterBufs<T> b) {
 // range's active groups at its offset (ranges in order, groups in order), and
 // its block 0 reduces the norms in a fixed order and steps the intercept.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void compact_range(int64_t ngroups, int64_t& g0, int64_t& g1) {
+__device__ __forceinline__ void compact_range(int64_t ngroups, int blk, int64_t& g0, int64_t& g1) {
   const int64_t per = (ngroups + kCompactBlocks - 1) / kCompactBlocks;
-  g0 = (int64_t)blockIdx.x * per;
+  g0 = (int64_t)blk * per;
   g1 = g0 + per < ngroups ? g0 + per : ngroups;
   if (g0 > ngroups) g0 = ngroups;
 }
 
 template <typename T>
-__global__ __launch_bounds__(1024) void k_count(int64_t ngroups, IterBufs<T> b) {
+__device__ __forceinline__ void count_body(int64_t ngroups, const IterBufs<T>& b, int blk) {
   __shared__ double red[5 * 16];
   int64_t g0, g1;
-  compact_range(ngroups, g0, g1);
+  compact_range(ngroups, blk, g0, g1);
   double s[5] = {0, 0, 0, 0, 0};
   for (int64_t gi = g0 + threadIdx.x; gi < g1; gi += 1024) {
     s[4] += b.gflag[gi] != 0;
@@ -130,23 +139,28 @@ __global__ __launch_bounds__(1024) void k_count(int64_t ngroups, IterBufs<T> b) 
   }
   block_sum<1024, 5, double>(s, red);
   if (threadIdx.x == 0) {
-    b.bcnt[blockIdx.x] = (int)s[4];
+    b.bcnt[blk] = (int)s[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) b.bnrm[blockIdx.x * 4 + k] = s[k];
+    for (int k = 0; k < 4; ++k) b.bnrm[blk * 4 + k] = s[k];
   }
 }
 
 template <typename T>
-__global__ __launch_bounds__(1024) void k_scatter(int64_t ngroups, IterBufs<T> b, double eta0,
-                                                  int step_intercept) {
+__global__ __launch_bounds__(1024) void k_count(int64_t ngroups, IterBufs<T> b) {
+  count_body<T>(ngroups, b, blockIdx.x);
+}
+
+template <typename T>
+__device__ __forceinline__ void scatter_body(int64_t ngroups, const IterBufs<T>& b, double eta0,
+                                             int step_intercept, int blk) {
   __shared__ int wcnt[16];
   __shared__ int base_s;
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
   int64_t g0, g1;
-  compact_range(ngroups, g0, g1);
+  compact_range(ngroups, blk, g0, g1);
   if (t == 0) {
     int off = 0;
-    for (int k = 0; k < (int)blockIdx.x; ++k) off += b.bcnt[k];
+    for (int k = 0; k < blk; ++k) off += b.bcnt[k];
     base_s = off;
   }
   __syncthreads();
@@ -167,7 +181,7 @@ __global__ __launch_bounds__(1024) void k_scatter(int64_t ngroups, IterBufs<T> b
     base += tot;
     __syncthreads();
   }
-  if (blockIdx.x == 0 && t == 0) {
+  if (blk == 0 && t == 0) {
     double s[4] = {0, 0, 0, 0};
     int total = 0;
     for (int k = 0; k < kCompactBlocks; ++k) {
@@ -187,6 +201,12 @@ __global__ __launch_bounds__(1024) void k_scatter(int64_t ngroups, IterBufs<T> b
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(1024) void k_scatter(int64_t ngroups, IterBufs<T> b, double eta0,
+                                                  int step_intercept) {
+  scatter_body<T>(ngroups, b, eta0, step_intercept, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int splits_in_use(int count, int smax, int min_per) {
   const int s = (count + min_per - 1) / min_per;
@@ -194,10 +214,10 @@ __device__ __forceinline__ int splits_in_use(int count, int smax, int min_per) {
 }
 
 template <int FMT, int RPL, typename T>
-__global__ __launch_bounds__(256) void k_axpy(Geom g, IterBufs<T> b, int smax, int min_per) {
+__device__ __forceinline__ void axpy_body(const Geom& g, const IterBufs<T>& b, int smax,
+                                          int min_per, int64_t bx, int split) {
   const int lane = threadIdx.x & 63;
-  const int64_t ch = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int split = blockIdx.y;
+  const int64_t ch = bx * 4 + (threadIdx.x >> 6);
   const int count = b.ctl->count;
   const int seff = splits_in_use(count, smax, min_per);
   if (split >= seff || ch >= g.nchunks()) return;
@@ -228,13 +248,18 @@ __global__ __launch_bounds__(256) void k_axpy(Geom g, IterBufs<T> b, int smax, i
   for (int r = 0; r < RPL; ++r) out[r] = acc[r] - off;
 }
 
+template <int FMT, int RPL, typename T>
+__global__ __launch_bounds__(256) void k_axpy(Geom g, IterBufs<T> b, int smax, int min_per) {
+  axpy_body<FMT, RPL, T>(g, b, smax, min_per, blockIdx.x, blockIdx.y);
+}
+
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_update(IterBufs<T> b, IterParams ip, int64_t n,
-                                                int64_t n_pad) {
+__device__ __forceinline__ void update_body(const IterBufs<T>& b, const IterParams& ip, int64_t n,
+                                            int64_t n_pad, int64_t blk, int64_t nblk) {
   __shared__ double red[8 * 4];
   __shared__ int last;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = blk * 256 + threadIdx.x;
   const int seff = splits_in_use(b.ctl->count, ip.smax, ip.min_per);
   double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (i < n) {
@@ -256,17 +281,17 @@ __global__ __launch_bounds__(256) void k_update(IterBufs<T> b, IterParams ip, in
   }
   block_sum<256, 8, double>(q, red);
   if (threadIdx.x == 0) {
-    for (int k = 0; k < 8; ++k) b.bpart[(int64_t)blockIdx.x * 8 + k] = q[k];
+    for (int k = 0; k < 8; ++k) b.bpart[blk * 8 + k] = q[k];
     __threadfence();
     const unsigned prev = atomicAdd(&b.ctl->blocks_done, 1u);
-    last = prev == gridDim.x - 1;
+    last = prev == (unsigned)(nblk - 1);
   }
   __syncthreads();
   if (!last) return;
   __threadfence();
   if (threadIdx.x < 8) {
     double s = 0;
-    for (unsigned blk = 0; blk < gridDim.x; ++blk) s += b.bpart[blk * 8 + threadIdx.x];
+    for (int64_t k = 0; k < nblk; ++k) s += b.bpart[k * 8 + threadIdx.x];
     red[threadIdx.x] = s;
   }
   __syncthreads();
@@ -282,6 +307,69 @@ __global__ __launch_bounds__(256) void k_update(IterBufs<T> b, IterParams ip, in
     c->iter += 1;
     c->blocks_done = 0u;
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_update(IterBufs<T> b, IterParams ip, int64_t n,
+                                                int64_t n_pad) {
+  update_body<T>(b, ip, n, n_pad, blockIdx.x, gridDim.x);
+}
+
+// ---------------------------------------------------------------------------
+// Grouped launches: one grid covers the blocks of every problem of a group.
+// off holds three prefix arrays of nprob + 1 block offsets (sweep, axpy,
+// update); the compaction gives every problem kCompactBlocks blocks.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int find_problem(const int* off, int nprob, int64_t blk) {
+  int lo = 0, hi = nprob - 1;   // largest i with off[i] <= blk
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((int64_t)off[mid] <= blk) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int FMT, int RPL, typename T>
+__global__ __launch_bounds__(256) void k_gsweep(const GroupDesc<T>* d, const int* off, int nprob) {
+  const int i = find_problem(off, nprob, blockIdx.x);
+  const Geom g = d[i].g;
+  const IterBufs<T> b = d[i].b;
+  sweep_body<FMT, RPL, T>(g, b, (int64_t)blockIdx.x - off[i]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_gcount(const GroupDesc<T>* d) {
+  const int i = blockIdx.x / kCompactBlocks;
+  const IterBufs<T> b = d[i].b;
+  count_body<T>(d[i].g.ngroups(), b, blockIdx.x % kCompactBlocks);
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_gscatter(const GroupDesc<T>* d) {
+  const int i = blockIdx.x / kCompactBlocks;
+  const IterBufs<T> b = d[i].b;
+  scatter_body<T>(d[i].g.ngroups(), b, d[i].ip.eta0, 1, blockIdx.x % kCompactBlocks);
+}
+
+template <int FMT, int RPL, typename T>
+__global__ __launch_bounds__(256) void k_gaxpy(const GroupDesc<T>* d, const int* off, int nprob) {
+  const int* o = off + (nprob + 1);
+  const int i = find_problem(o, nprob, blockIdx.x);
+  const Geom g = d[i].g;
+  const IterBufs<T> b = d[i].b;
+  const int64_t local = (int64_t)blockIdx.x - o[i];
+  const int64_t nx = (g.nchunks() + 3) / 4;
+  axpy_body<FMT, RPL, T>(g, b, d[i].ip.smax, d[i].ip.min_per, local % nx, (int)(local / nx));
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gupdate(const GroupDesc<T>* d, const int* off, int nprob) {
+  const int* o = off + 2 * (nprob + 1);
+  const int i = find_problem(o, nprob, blockIdx.x);
+  const IterBufs<T> b = d[i].b;
+  const IterParams ip = d[i].ip;
+  const int64_t n_pad = d[i].g.n_pad;
+  update_body<T>(b, ip, d[i].g.n, n_pad, (int64_t)blockIdx.x - o[i], n_pad / 256);
 }
 
 // r = X~beta + beta0 + z - y and sum(theta) for a given state.
@@ -352,6 +440,18 @@ static void launch_fmt(const Geom& g, const IterBufs<T>& b, const IterParams& ip
 }
 
 template <int FMT, int RPL, typename T>
+static void grouped_fmt(const GroupDesc<T>* d, const int* off, int nprob, const int64_t tot[3],
+                        hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  if (ev0) (void)hipEventRecord(ev0, s);
+  hipLaunchKernelGGL((k_gsweep<FMT, RPL, T>), dim3((unsigned)tot[0]), dim3(256), 0, s, d, off, nprob);
+  if (ev1) (void)hipEventRecord(ev1, s);
+  hipLaunchKernelGGL((k_gcount<T>), dim3((unsigned)(nprob * kCompactBlocks)), dim3(1024), 0, s, d);
+  hipLaunchKernelGGL((k_gscatter<T>), dim3((unsigned)(nprob * kCompactBlocks)), dim3(1024), 0, s, d);
+  hipLaunchKernelGGL((k_gaxpy<FMT, RPL, T>), dim3((unsigned)tot[1]), dim3(256), 0, s, d, off, nprob);
+  hipLaunchKernelGGL((k_gupdate<T>), dim3((unsigned)tot[2]), dim3(256), 0, s, d, off, nprob);
+}
+
+template <int FMT, int RPL, typename T>
 static void prepare_fmt(const Geom& g, const IterBufs<T>& b, const IterParams& ip, hipStream_t s) {
   const int64_t ng = g.ngroups();
   hipLaunchKernelGGL((k_flags<T>), dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, s, ng, b);
@@ -397,6 +497,19 @@ hipError_t launch_prepare_state(const Geom& g, const IterBufs<T>& b, const IterP
   PQR_DISPATCH(prepare_fmt, g, b, ip, s)
   return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_grouped_iteration(const Geom& g, const GroupDesc<T>* d, const int* off,
+                                    int nprob, const int64_t tot[3], hipStream_t s,
+                                    hipEvent_t ev0, hipEvent_t ev1) {
+  if (nprob < 1 || tot[0] < 1 || tot[1] < 1 || tot[2] < 1 || tot[0] > INT32_MAX ||
+      tot[1] > INT32_MAX || tot[2] > INT32_MAX || (int64_t)nprob * kCompactBlocks > INT32_MAX)
+    return hipErrorInvalidValue;
+  PQR_DISPATCH(grouped_fmt, d, off, nprob, tot, s, ev0, ev1)
+  return hipGetLastError();
+}
+template hipError_t launch_grouped_iteration<float>(const Geom&, const GroupDesc<float>*, const int*, int, const int64_t*, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_grouped_iteration<double>(const Geom&, const GroupDesc<double>*, const int*, int, const int64_t*, hipStream_t, hipEvent_t, hipEvent_t);
 
 template <typename T>
 hipError_t launch_active_list(const Geom& g, const IterBufs<T>& b, hipStream_t s) {

@@ -693,123 +693,259 @@ double default_mu(const pqr_ctx* ctx, const double* y) {
   return ctx->opt.mu_scale * std::sqrt(ctx->G + 1.0) / ((double)n * (sd > 0 ? sd : 1.0));
 }
 
+// One solve's host-side state: set-up, the checks between chunks of
+// iterations (H-norm monitor, FP64 certificate, best bounds) and the export.
+// pqr_solve drives one Run; pqr_solve_grouped drives many, with the iterations
+// of all of them in shared launches.
 template <typename T>
-pqr_status solve_impl(pqr_ctx* ctx, const double* y, double tau, double lambda,
-                      const double* weights, int start, const pqr_result* warm, pqr_result* out) {
-  const auto t0 = std::chrono::steady_clock::now();
-  TRY(validate_problem(ctx, y, tau, lambda, weights));
-  if (start == PQR_START_HOST && (!warm || !warm->beta_std)) {
-    ctx->err = "PQR_START_HOST needs warm->beta_std";
-    return PQR_ERR_INVALID_ARG;
-  }
-  if (start == PQR_START_DEVICE && !ctx->have_state) {
-    ctx->err = "PQR_START_DEVICE needs a previous solve on this context";
-    return PQR_ERR_INVALID_ARG;
-  }
-  double lmax = 0.0;
-  TRY(upload_problem<T>(ctx, y, tau, lambda, weights, &lmax, nullptr));
-  const double mu = ctx->opt.mu > 0 ? ctx->opt.mu
-                                    : (start == PQR_START_DEVICE ? ctx->state_mu : default_mu(ctx, y));
+struct Run {
+  pqr_ctx* ctx = nullptr;
+  std::chrono::steady_clock::time_point t0;
+  double tau = 0.0, mu = 0.0, lmax = 0.0, eta_scale = 1.0;
   IterParams ip{};
-  double eta_scale = 1.0;
-  TRY(set_eta<T>(ctx, mu, nullptr, eta_scale, ip, tau));
-  TRY(init_state<T>(ctx, start, warm ? warm->beta_std : nullptr, warm ? warm->z : nullptr,
-                    warm ? warm->theta : nullptr, ip));
-  ctx->have_state = true;
-  ctx->state_mu = mu;
-
-  const Geom& g = ctx->g;
-  hipStream_t s = ctx->s;
   int64_t it = 0, certs = 0, restarts = 0, sweeps = 0;
   double sweep_ms = 0.0;
   // Any iterate's P(beta) bounds P* from above and any feasible dual point's
   // value bounds it from below, so the gap certified so far is
   // min primal - max dual; the coefficients reported are the best primal ones.
   double best_primal = INFINITY, best_dual = -INFINITY, best_beta0 = 0.0;
-  auto track = [&](const Cert& c) -> pqr_status {
+  pqr_status status = PQR_ERR_NOT_CONVERGED;
+
+  bool active() const { return status == PQR_ERR_NOT_CONVERGED && it < ctx->opt.max_iter; }
+  int64_t next_chunk() const {
+    return std::min<int64_t>(ctx->opt.cert_every, ctx->opt.max_iter - it);
+  }
+  double best_gap() const {
+    return (best_primal - best_dual) / std::max(std::fabs(best_primal), 1e-300);
+  }
+
+  pqr_status track() {
+    Cert c{};
+    TRY(certificate<T>(ctx, tau, &c));
+    ++certs;
     best_dual = std::max(best_dual, c.dual);
     if (c.primal < best_primal) {
       best_primal = c.primal;
       Ctl cc;
-      HIPCHK(hipMemcpyAsync(&cc, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(ctx->beta_best, ctx->beta, g.p_pad * sizeof(T),
-                            hipMemcpyDeviceToDevice, s));
-      HIPCHK(hipStreamSynchronize(s));
+      HIPCHK(hipMemcpyAsync(&cc, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->s));
+      HIPCHK(hipMemcpyAsync(ctx->beta_best, ctx->beta, ctx->g.p_pad * sizeof(T),
+                            hipMemcpyDeviceToDevice, ctx->s));
+      HIPCHK(hipStreamSynchronize(ctx->s));
       best_beta0 = cc.beta0;
     }
+    if (best_gap() <= ctx->opt.tol_gap) status = PQR_OK;
     return PQR_OK;
-  };
-  auto best_gap = [&]() {
-    return (best_primal - best_dual) / std::max(std::fabs(best_primal), 1e-300);
-  };
-  if (ctx->opt.profile && ctx->events.empty()) {
-    ctx->events.resize(2 * (size_t)ctx->opt.cert_every);
-    for (auto& e : ctx->events) HIPCHK(hipEventCreate(&e));
   }
-  Cert cert{};
-  pqr_status status = PQR_ERR_NOT_CONVERGED;
-  TRY(certificate<T>(ctx, tau, &cert));
-  ++certs;
-  TRY(track(cert));
-  if (best_gap() <= ctx->opt.tol_gap) status = PQR_OK;
-  while (status != PQR_OK && it < ctx->opt.max_iter) {
-    const int64_t chunk = std::min<int64_t>(ctx->opt.cert_every, ctx->opt.max_iter - it);
-    const IterBufs<T> b = bufs<T>(ctx);
-    const bool prof = ctx->opt.profile != 0;
-    for (int64_t k = 0; k < chunk; ++k)
-      HIPCHK(launch_iteration<T>(g, b, ip, s, prof ? ctx->events[2 * k] : nullptr,
-                                 prof ? ctx->events[2 * k + 1] : nullptr));
+
+  pqr_status begin(pqr_ctx* c, const double* y, double tau_, double lambda, const double* weights,
+                   int start, const pqr_result* warm) {
+    ctx = c;
+    t0 = std::chrono::steady_clock::now();
+    tau = tau_;
+    TRY(validate_problem(ctx, y, tau, lambda, weights));
+    if (start == PQR_START_HOST && (!warm || !warm->beta_std)) {
+      ctx->err = "PQR_START_HOST needs warm->beta_std";
+      return PQR_ERR_INVALID_ARG;
+    }
+    if (start == PQR_START_DEVICE && !ctx->have_state) {
+      ctx->err = "PQR_START_DEVICE needs a previous solve on this context";
+      return PQR_ERR_INVALID_ARG;
+    }
+    TRY(upload_problem<T>(ctx, y, tau, lambda, weights, &lmax, nullptr));
+    mu = ctx->opt.mu > 0 ? ctx->opt.mu
+                         : (start == PQR_START_DEVICE ? ctx->state_mu : default_mu(ctx, y));
+    TRY(set_eta<T>(ctx, mu, nullptr, eta_scale, ip, tau));
+    TRY(init_state<T>(ctx, start, warm ? warm->beta_std : nullptr, warm ? warm->z : nullptr,
+                      warm ? warm->theta : nullptr, ip));
+    ctx->have_state = true;
+    ctx->state_mu = mu;
+    return track();
+  }
+
+  // After `chunk` more iterations have run (and the stream is idle).
+  pqr_status after_chunk(int64_t chunk) {
     it += chunk;
     Ctl c;
-    HIPCHK(hipMemcpyAsync(&c, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (prof) {
-      for (int64_t k = 0; k < chunk; ++k) {
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, ctx->events[2 * k], ctx->events[2 * k + 1]));
-        sweep_ms += ms;
-      }
-      sweeps += chunk;
-    }
+    HIPCHK(hipMemcpyAsync(&c, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->s));
+    HIPCHK(hipStreamSynchronize(ctx->s));
     if (!std::isfinite(c.delta) || c.n_increase > 25) {
       // the H-norm successive difference grows: the metric is not positive
       // definite (eta_g below mu Lambda_max); double eta and restart
       if (++restarts > 2) {
         ctx->err = "H-norm monitor: successive differences keep growing after doubling eta twice";
         status = PQR_ERR_DIVERGED;
-        break;
+        return PQR_OK;
       }
       eta_scale *= 2.0;
       TRY(set_eta<T>(ctx, mu, nullptr, eta_scale, ip, tau));
       TRY(init_state<T>(ctx, PQR_START_ZERO, nullptr, nullptr, nullptr, ip));
-      continue;
+      return PQR_OK;
     }
-    TRY(certificate<T>(ctx, tau, &cert));
-    ++certs;
-    TRY(track(cert));
-    if (best_gap() <= ctx->opt.tol_gap) status = PQR_OK;
+    return track();
   }
-  cert.primal = best_primal;
-  cert.dual = best_dual;
-  cert.gap = best_primal - best_dual;
-  cert.rel_gap = best_gap();
-  if (out) {
-    TRY(export_state<T>(ctx, out, ctx->beta_best, best_beta0));
-    out->iters = it;
-    out->certs = certs;
-    out->x_passes = it + certs + 1;
-    out->primal = cert.primal;
-    out->dual = cert.dual;
-    out->rel_gap = cert.rel_gap;
-    out->lambda_max = lmax;
-    out->mu = mu;
-    out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    out->sweep_ms = sweep_ms;
-    out->sweep_launches = sweeps;
+
+  pqr_status finish(pqr_result* out) {
+    if (out) {
+      TRY(export_state<T>(ctx, out, ctx->beta_best, best_beta0));
+      out->iters = it;
+      out->certs = certs;
+      out->x_passes = it + certs + 1;
+      out->primal = best_primal;
+      out->dual = best_dual;
+      out->rel_gap = best_gap();
+      out->lambda_max = lmax;
+      out->mu = mu;
+      out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      out->sweep_ms = sweep_ms;
+      out->sweep_launches = sweeps;
+    }
+    if (status == PQR_ERR_NOT_CONVERGED)
+      ctx->err = "max_iter reached with relative gap " + std::to_string(best_gap());
+    return status;
   }
-  if (status == PQR_ERR_NOT_CONVERGED)
-    ctx->err = "max_iter reached with relative gap " + std::to_string(cert.rel_gap);
-  return status;
+};
+
+template <typename T>
+pqr_status solve_impl(pqr_ctx* ctx, const double* y, double tau, double lambda,
+                      const double* weights, int start, const pqr_result* warm, pqr_result* out) {
+  Run<T> run;
+  TRY(run.begin(ctx, y, tau, lambda, weights, start, warm));
+  const Geom& g = ctx->g;
+  hipStream_t s = ctx->s;
+  const bool prof = ctx->opt.profile != 0;
+  if (prof && ctx->events.empty()) {
+    ctx->events.resize(2 * (size_t)ctx->opt.cert_every);
+    for (auto& e : ctx->events) HIPCHK(hipEventCreate(&e));
+  }
+  while (run.active()) {
+    const int64_t chunk = run.next_chunk();
+    const IterBufs<T> b = bufs<T>(ctx);
+    for (int64_t k = 0; k < chunk; ++k)
+      HIPCHK(launch_iteration<T>(g, b, run.ip, s, prof ? ctx->events[2 * k] : nullptr,
+                                 prof ? ctx->events[2 * k + 1] : nullptr));
+    HIPCHK(hipStreamSynchronize(s));
+    if (prof) {
+      for (int64_t k = 0; k < chunk; ++k) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ctx->events[2 * k], ctx->events[2 * k + 1]));
+        run.sweep_ms += ms;
+      }
+      run.sweeps += chunk;
+    }
+    TRY(run.after_chunk(chunk));
+  }
+  return run.finish(out);
+}
+
+// Many independent problems, each on its own context, iterated together: every
+// iteration of every still-running problem is one set of five grouped launches
+// on the first context's stream; set-up, certificates and exports stay per
+// problem.
+template <typename T>
+pqr_status grouped_impl(int nprob, pqr_ctx* const* ctxs, const double* const* ys,
+                        const double* taus, const double* lambdas, const double* const* weights,
+                        pqr_result* outs, pqr_status* statuses) {
+  pqr_ctx* c0 = ctxs[0];
+  pqr_ctx* ctx = c0;   // device errors of the shared launches are reported here
+  hipStream_t s = c0->s;
+  std::vector<Run<T>> runs(nprob);
+  std::vector<pqr_status> st(nprob, PQR_OK);
+  for (int i = 0; i < nprob; ++i) {
+    st[i] = runs[i].begin(ctxs[i], ys[i], taus[i], lambdas[i], weights ? weights[i] : nullptr,
+                          PQR_START_ZERO, nullptr);
+    if (st[i] != PQR_OK) runs[i].status = st[i];
+  }
+  const bool prof = c0->opt.profile != 0;
+  // device table and events, released on every exit path
+  struct Owned {
+    GroupDesc<T>* desc = nullptr;
+    int* off = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    ~Owned() {
+      if (desc) (void)hipFree(desc);
+      if (off) (void)hipFree(off);
+      for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    }
+  } own;
+  hipEvent_t* ev = own.ev;
+  if (prof)
+    for (int k = 0; k < 2; ++k) HIPCHK(hipEventCreate(&ev[k]));
+  double sweep_ms = 0.0;
+  int64_t sweeps = 0;
+  pqr_status fail = PQR_OK;
+  if (hipMalloc(&own.desc, sizeof(GroupDesc<T>) * nprob) != hipSuccess ||
+      hipMalloc(&own.off, sizeof(int) * 3 * (nprob + 1)) != hipSuccess) {
+    c0->err = "grouped solve: out of device memory for the problem table";
+    fail = PQR_ERR_OOM;
+  }
+  GroupDesc<T>* desc_d = own.desc;
+  int* off_d = own.off;
+  std::vector<GroupDesc<T>> desc;
+  std::vector<int> off;
+  while (fail == PQR_OK) {
+    std::vector<int> act;
+    for (int i = 0; i < nprob; ++i)
+      if (runs[i].ctx && st[i] == PQR_OK && runs[i].active()) act.push_back(i);
+    if (act.empty()) break;
+    int64_t chunk = INT64_MAX;
+    for (int i : act) chunk = std::min(chunk, runs[i].next_chunk());
+    const int na = (int)act.size();
+    desc.resize(na);
+    off.assign(3 * (na + 1), 0);
+    int64_t tot[3] = {0, 0, 0};
+    for (int k = 0; k < na; ++k) {
+      pqr_ctx* c = ctxs[act[k]];
+      desc[k].g = c->g;
+      desc[k].b = bufs<T>(c);
+      desc[k].ip = runs[act[k]].ip;
+      const int64_t nb[3] = {(c->g.ngroups() + 3) / 4,
+                             ((c->g.nchunks() + 3) / 4) * runs[act[k]].ip.smax,
+                             c->g.n_pad / 256};
+      for (int q = 0; q < 3; ++q) {
+        off[q * (na + 1) + k] = (int)tot[q];
+        tot[q] += nb[q];
+      }
+    }
+    for (int q = 0; q < 3; ++q) {
+      if (tot[q] > INT32_MAX) {
+        c0->err = "grouped solve: too many blocks in one launch";
+        fail = PQR_ERR_UNSUPPORTED;
+      }
+      off[q * (na + 1) + na] = (int)tot[q];
+    }
+    if (fail != PQR_OK) break;
+    HIPCHK(hipMemcpyAsync(desc_d, desc.data(), sizeof(GroupDesc<T>) * na, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(off_d, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice, s));
+    for (int64_t k = 0; k < chunk; ++k) {
+      const bool rec = prof && k == 0;
+      HIPCHK(launch_grouped_iteration<T>(c0->g, desc_d, off_d, na, tot, s, rec ? ev[0] : nullptr,
+                                         rec ? ev[1] : nullptr));
+      if (rec) {
+        HIPCHK(hipStreamSynchronize(s));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
+        sweep_ms += ms * (double)chunk;   // the first launch of a chunk stands for the chunk
+        sweeps += chunk;
+      }
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    for (int i : act) {
+      st[i] = runs[i].after_chunk(chunk);
+      if (st[i] != PQR_OK) runs[i].status = st[i];
+    }
+  }
+  pqr_status first = fail;
+  for (int i = 0; i < nprob; ++i) {
+    if (runs[i].ctx && st[i] == PQR_OK) {
+      runs[i].sweep_ms = sweep_ms;
+      runs[i].sweeps = sweeps;
+      st[i] = runs[i].finish(outs ? &outs[i] : nullptr);
+    }
+    if (statuses) statuses[i] = st[i];
+    if (first == PQR_OK && st[i] != PQR_OK) first = st[i];
+  }
+  return first;
 }
 
 }  // namespace
@@ -825,6 +961,32 @@ extern "C" pqr_status pqr_solve(pqr_ctx* ctx, const double* y, double tau, doubl
   if (ctx->opt.iter_prec == PQR_ITER_F64)
     return solve_impl<double>(ctx, y, tau, lambda, weights, start, warm, out);
   return solve_impl<float>(ctx, y, tau, lambda, weights, start, warm, out);
+}
+
+extern "C" pqr_status pqr_solve_grouped(int nprob, pqr_ctx* const* ctxs, const double* const* ys,
+                                        const double* taus, const double* lambdas,
+                                        const double* const* weights, pqr_result* outs,
+                                        pqr_status* statuses) {
+  if (nprob < 1 || !ctxs || !ys || !taus || !lambdas) return PQR_ERR_INVALID_ARG;
+  for (int i = 0; i < nprob; ++i)
+    if (!ctxs[i]) return PQR_ERR_INVALID_ARG;
+  pqr_ctx* c0 = ctxs[0];
+  for (int i = 0; i < nprob; ++i) {
+    for (int k = 0; k < i; ++k)
+      if (ctxs[k] == ctxs[i]) {
+        c0->err = "pqr_solve_grouped: a context appears twice";
+        return PQR_ERR_INVALID_ARG;
+      }
+    if (ctxs[i]->opt.iter_prec != c0->opt.iter_prec || ctxs[i]->g.fmt != c0->g.fmt ||
+        ctxs[i]->g.rpl != c0->g.rpl) {
+      c0->err = "pqr_solve_grouped: every context needs the same store format, rows per lane "
+                "and iterate precision";
+      return PQR_ERR_UNSUPPORTED;
+    }
+  }
+  if (c0->opt.iter_prec == PQR_ITER_F64)
+    return grouped_impl<double>(nprob, ctxs, ys, taus, lambdas, weights, outs, statuses);
+  return grouped_impl<float>(nprob, ctxs, ys, taus, lambdas, weights, outs, statuses);
 }
 
 namespace {

@@ -67,6 +67,24 @@ template <typename T>
 hipError_t launch_iteration(const Geom& g, const IterBufs<T>& b, const IterParams& ip,
                             hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
+// One problem of a grouped launch: its store geometry, buffers and parameters.
+template <typename T>
+struct GroupDesc {
+  Geom g;
+  IterBufs<T> b;
+  IterParams ip;
+};
+
+// One FS-QRPPA iteration of every problem in d[0..nprob) with five launches in
+// total.  Every problem shares g.fmt and g.rpl (g is any of their geometries);
+// off (device) holds three prefix arrays of nprob + 1 block offsets: the sweep's
+// ceil(ngroups / 4) blocks, the axpy's ceil(nchunks / 4) * smax blocks and the
+// update's n_pad / 256 blocks of each problem, and tot[k] = off[k][nprob].
+template <typename T>
+hipError_t launch_grouped_iteration(const Geom& g, const GroupDesc<T>* d, const int* off,
+                                    int nprob, const int64_t tot[3], hipStream_t s,
+                                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+
 // Recompute the cached residual r = X~beta + beta0 + z - y and sum(theta) for a
 // given state (after a warm start); also rebuilds the active list.  ip.fit
 // derives z and/or theta from beta instead (see IterParams).
