@@ -18,11 +18,9 @@
 namespace pqr {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
 
 constexpr int kBS = 3;                  // digit slices of theta
-constexpr int kBGroups = 8;             // column groups per workgroup in the GEMM
-constexpr int kBRows = 128;             // rows staged in LDS per step
-constexpr int kBStride = kBRows + 16;   // padded LDS row stride (bank spread)
 
 // ---------------------------------------------------------------------------
 // Digits: T = round(theta / c * 2^(7S-1)), balanced base-128 digits, and the
@@ -72,106 +70,166 @@ __global__ void k_bdsum(BatchBufs b, int nblk, int Kp) {
 }
 
 // ---------------------------------------------------------------------------
-// V = X~^T Theta on the int8 MFMA (16x16x64): one wavefront per 16 right-hand
-// sides, kBGroups column groups per workgroup, X staged through LDS; epilogue:
-// the weighted soft threshold of eq. beta_update for every (column, k).
+// V = X~^T Theta on the int8 MFMA (16x16x64).  A wavefront owns GW column
+// groups over all rows and TW right-hand-side tiles (16 k each): per 64-row
+// step it loads one A fragment per group straight from the blocked store (lane:
+// column lane % 16, rows 16 (lane / 16) .. +15 of the step, 16 contiguous bytes)
+// and one B fragment per (tile, slice) of the digits, and issues GW * TW * S
+// MFMAs.  With more than TW tiles, the block's wavefronts split the tiles of the
+// same groups (their A loads meet in the caches; HBM reads X once).  The next
+// step's fragments are loaded before this step's MFMAs; no LDS, no barriers.
+// Epilogue: the weighted soft threshold of eq. beta_update for every (column,
+// k) and per (group, tile) a 16-bit mask of the columns nonzero for some k.
 // ---------------------------------------------------------------------------
-template <int NRT>
-__global__ __launch_bounds__(NRT * 64) void k_bgemm(Geom g, BatchBufs b, int Kp) {
-  __shared__ __attribute__((aligned(16))) uint8_t xs[kBGroups * kGroup * kBStride];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t grp0 = (int64_t)blockIdx.x * kBGroups;
+template <int TW, int GW>
+__global__ __launch_bounds__(256, 2) void k_bgemm(Geom g, BatchBufs b, int Kp, int wps) {
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+  const int nrt = Kp / 16;
   const int64_t ng = g.ngroups();
-  v4i acc[kBGroups][kBS];
+  // wps wavefronts share one set of GW groups; wavefront wv % wps takes tiles r0..
+  const int64_t gw0 = ((int64_t)blockIdx.x * (4 / wps) + wv / wps) * GW;
+  const int r0 = (wv % wps) * TW;
+  if (gw0 >= ng || r0 >= nrt) return;        // the whole wavefront (no barriers below)
+  const int col = lane & 15, kq = lane >> 4;
+  v4i acc[GW][TW][kBS];
 #pragma unroll
-  for (int q = 0; q < kBGroups; ++q)
+  for (int q = 0; q < GW; ++q)
 #pragma unroll
-    for (int s = 0; s < kBS; ++s) acc[q][s] = v4i{0, 0, 0, 0};
-  const int rhs = wv * 16 + (lane & 15);   // B-operand column of this lane
-  const int kq = lane >> 4;                // 16-row quarter of a 64-row step
+    for (int r = 0; r < TW; ++r)
+#pragma unroll
+      for (int s = 0; s < kBS; ++s) acc[q][r][s] = v4i{0, 0, 0, 0};
+  const int64_t nsteps = g.nchunks() * 16;   // 64-row steps (1024-row chunks)
+  const bool tile_ok[2] = {true, TW > 1 && r0 + 1 < nrt};
+  // Buffer loads: a lane's offset is fixed (one VGPR per fragment), the step's
+  // part is a wave-uniform SGPR offset; no per-step address arithmetic.
+  // A: segments of the wave's groups, from the first group's chunk 0 (a group
+  // past the last one re-reads the last group; the epilogue skips it).
   const int64_t nch = g.nchunks();
-  constexpr int kLoads = kBGroups * kGroup * (kBRows / 16);   // uint4 per step
-  for (int64_t ch = 0; ch < nch; ++ch) {
-    for (int sub = 0; sub < 1024 / kBRows; ++sub) {
-      __syncthreads();
-      for (int idx = threadIdx.x; idx < kLoads; idx += NRT * 64) {
-        const int q = idx / (kGroup * (kBRows / 16));
-        const int rem = idx - q * (kGroup * (kBRows / 16));
-        const int c = rem / (kBRows / 16), part = rem - c * (kBRows / 16);
-        uint4 v = {0u, 0u, 0u, 0u};
-        if (grp0 + q < ng)
-          v = *reinterpret_cast<const uint4*>(g.seg((grp0 + q) * kGroup + c, ch) + sub * kBRows +
-                                              part * 16);
-        *reinterpret_cast<uint4*>(&xs[(q * kGroup + c) * kBStride + part * 16]) = v;
-      }
-      __syncthreads();
-      const int64_t rowbase = ch * 1024 + sub * kBRows;
+  const int64_t cstride = kGroup * g.seg_bytes;   // next chunk of a group
+  const int64_t gstride = nch * cstride;           // next group
+  const uint8_t* abase = g.X + gw0 * gstride;
+  const int64_t arem = g.store_bytes() - gw0 * gstride;
+  const __amdgpu_buffer_rsrc_t arsrc = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)abase, (short)0, (int)(arem < 0x7fffffffll ? arem : 0x7fffffffll), 0x00020000);
+  uint32_t aoff[GW];
 #pragma unroll
-      for (int ks = 0; ks < kBRows / 64; ++ks) {
-        v4i bf[kBS];
+  for (int q = 0; q < GW; ++q)
+    aoff[q] = (uint32_t)((gw0 + q < ng ? q : ng - 1 - gw0) * gstride + col * g.seg_bytes + kq * 16);
+  // B: digit rows (slice s, rhs (r0 + r)*16 + col), rows 16*kq .. of each step
+  // (a tile past the last one re-reads tile r0; the epilogue skips it)
+  const int64_t dbytes = (int64_t)kBS * Kp * g.n_pad;
+  const __amdgpu_buffer_rsrc_t brsrc = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)b.dig, (short)0, (int)(dbytes < 0x7fffffffll ? dbytes : 0x7fffffffll), 0x00020000);
+  uint32_t boff[TW][kBS];
 #pragma unroll
-        for (int s = 0; s < kBS; ++s) {
-          const uint4 t = *reinterpret_cast<const uint4*>(
-              b.dig + ((int64_t)s * Kp + rhs) * g.n_pad + rowbase + ks * 64 + kq * 16);
-          bf[s] = v4i{(int)t.x, (int)t.y, (int)t.z, (int)t.w};
-        }
+  for (int r = 0; r < TW; ++r)
 #pragma unroll
-        for (int q = 0; q < kBGroups; ++q) {
-          const uint4 t = *reinterpret_cast<const uint4*>(
-              &xs[(q * kGroup + (lane & 15)) * kBStride + ks * 64 + kq * 16]);
-          const v4i af = v4i{(int)t.x, (int)t.y, (int)t.z, (int)t.w};
+    for (int s = 0; s < kBS; ++s)
+      boff[r][s] = (uint32_t)(((int64_t)s * Kp + (r0 + (tile_ok[r] ? r : 0)) * 16 + col) * g.n_pad +
+                              kq * 16);
+  auto load_a = [&](int64_t t, v4i (&af)[GW]) {
+    const int so = (int)((t >> 4) * cstride + (t & 15) * 64);
 #pragma unroll
-          for (int s = 0; s < kBS; ++s)
-            acc[q][s] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf[s], acc[q][s], 0, 0, 0);
-        }
-      }
+    for (int q = 0; q < GW; ++q) {
+      const v4u v = __builtin_amdgcn_raw_buffer_load_b128(arsrc, (int)aoff[q], so, 0);
+      af[q] = v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
     }
+  };
+  auto load_b = [&](int64_t t, v4i (&bf)[TW][kBS]) {
+    const int so = (int)(t * 64);
+#pragma unroll
+    for (int r = 0; r < TW; ++r)
+#pragma unroll
+      for (int s = 0; s < kBS; ++s) {
+        const v4u v = __builtin_amdgcn_raw_buffer_load_b128(brsrc, (int)boff[r][s], so, 0);
+        bf[r][s] = v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
+      }
+  };
+  // Two fragment sets in ping-pong (the step count is even: 16 per chunk): a
+  // set is reloaded for the step after next right after its MFMAs issue, so
+  // the other set's loads are in flight while these MFMAs run and no register
+  // is copied.  Loads past the end re-read the last step (in bounds).
+  v4i aS[2][GW], bS[2][TW][kBS];
+  load_b(0, bS[0]);
+  load_a(0, aS[0]);
+  __builtin_amdgcn_sched_barrier(0);   // set 0 strictly older than set 1 on entry
+  load_b(1, bS[1]);
+  load_a(1, aS[1]);
+  __builtin_amdgcn_sched_barrier(0);
+  auto mma = [&](const v4i (&af)[GW], const v4i (&bf)[TW][kBS]) {
+#pragma unroll
+    for (int q = 0; q < GW; ++q)
+#pragma unroll
+      for (int r = 0; r < TW; ++r)
+#pragma unroll
+        for (int s = 0; s < kBS; ++s)
+          acc[q][r][s] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[q], bf[r][s], acc[q][r][s], 0, 0, 0);
+  };
+  // (scheduling barriers keep each set's reload between the two MFMA phases)
+  for (int64_t t = 0; t < nsteps; t += 2) {
+    mma(aS[0], bS[0]);
+    __builtin_amdgcn_sched_barrier(0);
+    const int64_t t2 = t + 2 < nsteps ? t + 2 : nsteps - 2;
+    load_b(t2, bS[0]);
+    load_a(t2, aS[0]);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(aS[1], bS[1]);
+    __builtin_amdgcn_sched_barrier(0);
+    load_b(t2 + 1, bS[1]);
+    load_a(t2 + 1, aS[1]);
+    __builtin_amdgcn_sched_barrier(0);
   }
-  // epilogue: lane holds columns m = 4*kq + e (e = 0..3) of each group, rhs = this lane's
-  const int k = rhs;
-  const bool live = k < b.K;
-  const double unit = live ? b.scale[k] / (double)(1 << (7 * kBS - 1)) : 0.0;
-  const double tq = live ? (double)b.tsumq[k] : 0.0;
-  const float lamk = live ? b.lam[k] : 0.f;
+  // epilogue: lane holds columns 4*kq + e (e = 0..3) of each group for rhs (r0+r)*16 + col
 #pragma unroll
-  for (int q = 0; q < kBGroups; ++q) {
-    const int64_t grp = grp0 + q;
-    if (grp >= ng) break;
-    const float eta = b.geta[grp];
-    bool nzany = false;
+  for (int r = 0; r < TW; ++r) {
+    if (!tile_ok[r]) break;
+    const int k = (r0 + r) * 16 + col;
+    const bool live = k < b.K && b.kact[k] != 0;   // frozen: beta kept, out of the union
+    const double unit = live ? b.scale[k] / (double)(1 << (7 * kBS - 1)) : 0.0;
+    const double tq = live ? (double)b.tsumq[k] : 0.0;
+    const float lamk = live ? b.lam[k] : 0.f;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int64_t j = grp * kGroup + 4 * kq + e;
-      long long P = 0;
+    for (int q = 0; q < GW; ++q) {
+      const int64_t grp = gw0 + q;
+      if (grp >= ng) break;
+      const float eta = b.geta[grp];
+      uint32_t cmask = 0;   // bit c: column c of the group is nonzero for some k of the tile
 #pragma unroll
-      for (int s = 0; s < kBS; ++s) P = P * 128 + (long long)acc[q][s][e];
-      // x~_j^T theta_k = (x_j^T theta_k - m_j sum theta_k) / s_j in the quantised theta
-      const double v = ((double)P - (double)b.cm[j] * tq) * unit * (double)b.cinv[j];
-      float* bp = b.beta + (int64_t)k * g.p_pad + j;
-      if (live) {
-        const float bo = *bp;
-        const float lj = lamk * b.w[j];
-        const float a = eta * bo + (float)v;
-        const float bn = (fmaxf(a - lj, 0.f) - fmaxf(-a - lj, 0.f)) / eta;   // eq. beta_update
-        *bp = bn;
-        nzany |= bn != 0.f;
+      for (int e = 0; e < 4; ++e) {
+        const int64_t j = grp * kGroup + 4 * kq + e;
+        long long P = 0;
+#pragma unroll
+        for (int s = 0; s < kBS; ++s) P = P * 128 + (long long)acc[q][r][s][e];
+        // x~_j^T theta_k = (x_j^T theta_k - m_j sum theta_k) / s_j in the quantised theta
+        const double v = ((double)P - (double)b.cm[j] * tq) * unit * (double)b.cinv[j];
+        float* bp = b.beta + (int64_t)k * g.p_pad + j;
+        if (live) {
+          const float bo = *bp;
+          const float lj = lamk * b.w[j];
+          const float a = eta * bo + (float)v;
+          const float bn = (fmaxf(a - lj, 0.f) - fmaxf(-a - lj, 0.f)) / eta;   // eq. beta_update
+          *bp = bn;
+        }
+        // lanes 16 kq .. 16 kq + 15 hold column 4 kq + e for the tile's 16 k
+        const unsigned long long bal = __ballot(live && *bp != 0.f);
+#pragma unroll
+        for (int h = 0; h < 4; ++h)
+          cmask |= (((bal >> (16 * h)) & 0xffffull) != 0ull ? 1u : 0u) << (4 * h + e);
       }
-    }
-    const unsigned long long bal = __ballot(nzany);
-    if (lane == 0) {
-      const uint32_t m16 = (uint32_t)((bal | (bal >> 16) | (bal >> 32) | (bal >> 48)) & 0xffffull);
-      b.mask[grp * (Kp / 16) + wv] = m16;
+      if (lane == 0) b.mask[grp * nrt + r0 + r] = cmask;
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Union of active groups (any right-hand side), in order; intercepts.
+// Union of the nonzero columns (any active right-hand side), in increasing
+// order, from the per-(group, tile) column masks; intercepts.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool bflag(const BatchBufs& b, int64_t gi, int nrt) {
+__device__ __forceinline__ uint32_t bcols(const BatchBufs& b, int64_t gi, int nrt) {
   uint32_t m = 0;
   for (int t = 0; t < nrt; ++t) m |= b.mask[gi * nrt + t];
-  return m != 0;
+  return m;
 }
 
 __global__ __launch_bounds__(1024) void k_bcount(int64_t ngroups, BatchBufs b, int nrt) {
@@ -179,14 +237,14 @@ __global__ __launch_bounds__(1024) void k_bcount(int64_t ngroups, BatchBufs b, i
   const int64_t per = (ngroups + kCompactBlocks - 1) / kCompactBlocks;
   const int64_t g0 = (int64_t)blockIdx.x * per, g1 = g0 + per < ngroups ? g0 + per : ngroups;
   double s[1] = {0};
-  for (int64_t gi = g0 + threadIdx.x; gi < g1; gi += 1024) s[0] += bflag(b, gi, nrt);
+  for (int64_t gi = g0 + threadIdx.x; gi < g1; gi += 1024) s[0] += __popc(bcols(b, gi, nrt));
   block_sum<1024, 1, double>(s, red);
   if (threadIdx.x == 0) b.bcnt[blockIdx.x] = (int)s[0];
 }
 
 __global__ __launch_bounds__(1024) void k_bscatter(int64_t ngroups, BatchBufs b, int nrt,
                                                    double eta0, int Kp) {
-  __shared__ int wcnt[16];
+  __shared__ int wsum[16];
   __shared__ int base_s;
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
   const int64_t per = (ngroups + kCompactBlocks - 1) / kCompactBlocks;
@@ -202,14 +260,21 @@ __global__ __launch_bounds__(1024) void k_bscatter(int64_t ngroups, BatchBufs b,
   int base = base_s;
   for (int64_t tile = g0; tile < g1; tile += 1024) {
     const int64_t gi = tile + t;
-    const bool f = gi < g1 && bflag(b, gi, nrt);
-    const unsigned long long bal = __ballot(f);
-    const int before = __popcll(bal & ((1ull << lane) - 1ull));
-    if (lane == 0) wcnt[wid] = __popcll(bal);
+    const uint32_t m = gi < g1 ? bcols(b, gi, nrt) : 0u;
+    const int pc = __popc(m);
+    // inclusive scan of the popcounts in the wavefront, then across wavefronts
+    int incl = pc;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(incl, off);
+      if (lane >= off) incl += v;
+    }
+    if (lane == 63) wsum[wid] = incl;
     __syncthreads();
     int woff = 0, tot = 0;
-    for (int w = 0; w < 16; ++w) { woff += w < wid ? wcnt[w] : 0; tot += wcnt[w]; }
-    if (f) b.list[base + woff + before] = (int)gi;
+    for (int w = 0; w < 16; ++w) { woff += w < wid ? wsum[w] : 0; tot += wsum[w]; }
+    int pos = base + woff + incl - pc;
+    for (uint32_t mm = m; mm; mm &= mm - 1) b.list[pos++] = (int)(gi * kGroup + __ffs(mm) - 1);
     base += tot;
     __syncthreads();
   }
@@ -220,67 +285,207 @@ __global__ __launch_bounds__(1024) void k_bscatter(int64_t ngroups, BatchBufs b,
       *b.count = total;
     }
     // intercepts (lambda_0 = 0): beta0_k += sum_i theta_ik / eta_0
-    for (int k = t; k < b.K; k += 1024) b.beta0[k] += b.tsum[k] / eta0;
+    for (int k = t; k < b.K; k += 1024)
+      if (b.kact[k]) b.beta0[k] += b.tsum[k] / eta0;
   }
 }
 
 // ---------------------------------------------------------------------------
-// S = X~ B over the union list: one wavefront per row chunk and 4 right-hand
-// sides, splits of the list along grid.y, FP64 partials.
+// S = X~ B over the union list on the int8 MFMA.  The coefficients on the raw
+// column scale, b'_kj = beta_kj / s_j, are written in fixed point as
+// U_kj = round(b'_kj / d_k * 2^27) with d_k a power of two >= max_j |b'_kj|, cut
+// into four balanced base-128 digits (|digit| <= 64); every product and sum of
+// a slice is exact in int32, so S_ik = d_k 2^-27 (sum_j x_ij U_kj - sum_j m_j U_kj)
+// is exactly X~ times the quantised coefficients (2^-28 d_k each), combined in
+// int64 and FP64 per split of the union.
 // ---------------------------------------------------------------------------
+constexpr int kCS = 4;                  // digit slices of the coefficients
+constexpr int kDigitBlocks = 256;       // blocks of the coefficient digit kernels
+constexpr int kCBits = 7 * kCS - 1;     // fixed-point bits below d_k
+
 __device__ __forceinline__ int bsplits(int count, int smax, int min_per) {
   const int s = (count + min_per - 1) / min_per;
   return s < 1 ? 1 : (s > smax ? smax : s);
 }
 
-__global__ __launch_bounds__(256) void k_baxpy(Geom g, BatchBufs b, int Kp, int smax,
-                                               int min_per) {
-  const int lane = threadIdx.x & 63;
-  const int64_t ch = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int split = blockIdx.y;
-  const int k0 = blockIdx.z * 4;
+// The union list is read in "virtual groups" of 16 consecutive entries (entry
+// 16 e + c is column c of virtual group e; entries past the count are zero).
+//
+// Per-block maxima of |b'_kj| over the union (kDigitBlocks blocks; thread t
+// takes entry t % 16 of each virtual group and the right-hand sides t / 16 + 16 i).
+__global__ __launch_bounds__(256) void k_bbmax(Geom g, BatchBufs b, int Kp) {
+  const int t = threadIdx.x, c = t & 15, nrt = Kp / 16;
   const int count = *b.count;
-  const int seff = bsplits(count, smax, min_per);
-  if (split >= seff || ch >= g.nchunks()) return;
-  const int per = (count + seff - 1) / seff;
-  const int e0 = split * per;
-  const int e1 = e0 + per < count ? e0 + per : count;
-  const int64_t row0 = ch * 1024 + (int64_t)lane * 16;
-  double acc[16][4];
-#pragma unroll
-  for (int r = 0; r < 16; ++r)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[r][q] = 0;
-  double off[4] = {0, 0, 0, 0};
-  for (int e = e0; e < e1; ++e) {
-    const int64_t grp = b.list[e];
-    for (int c = 0; c < kGroup; ++c) {
-      const int64_t j = grp * kGroup + c;
-      double bj[4];
-      bool any = false;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        bj[q] = (double)b.beta[(int64_t)(k0 + q) * g.p_pad + j] * (double)b.cinv[j];
-        any |= bj[q] != 0.0;
-      }
-      if (any) {
-        double x[16];
-        load_rows<I8, 16, double>(g.seg(j, ch), (int64_t)lane * 16, x);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-#pragma unroll
-          for (int r = 0; r < 16; ++r) acc[r][q] = fma(x[r], bj[q], acc[r][q]);
-          off[q] = fma((double)b.cm[j], bj[q], off[q]);
-        }
-      }
+  const int nvg = (count + 15) / 16;
+  double mx[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int e = blockIdx.x; e < nvg; e += kDigitBlocks) {
+    if (16 * e + c >= count) continue;
+    const int64_t j = b.list[16 * e + c];
+    const double ci = (double)b.cinv[j];
+    for (int r = 0; r < nrt; ++r) {
+      const int k = (t >> 4) + 16 * r;
+      mx[r] = fmax(mx[r], fabs((double)b.beta[(int64_t)k * g.p_pad + j] * ci));
     }
   }
+  for (int r = 0; r < nrt; ++r) {
+    double v = mx[r];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    double* out = b.partial + ((int64_t)split * Kp + k0 + q) * g.n_pad + row0;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) out[r] = acc[r][q] - off[q];
+    for (int off = 8; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    if (c == 0) b.pmax[(int64_t)blockIdx.x * Kp + (t >> 4) + 16 * r] = v;
   }
+}
+
+// Digit slices of the union coefficients (list order, zero past the count) and
+// the per-block sums of m_j U_kj; d_k from the maxima of k_bbmax.
+__global__ __launch_bounds__(256) void k_bbdigits(Geom g, BatchBufs b, int Kp) {
+  __shared__ double dk[128];
+  const int t = threadIdx.x, c = t & 15, nrt = Kp / 16;
+  if (t < Kp) {
+    double mx = 0;
+    for (int q = 0; q < kDigitBlocks; ++q) mx = fmax(mx, b.pmax[(int64_t)q * Kp + t]);
+    int ex = 0;
+    const double fr = frexp(mx > 0 ? mx : 1.0, &ex);
+    const double d = ldexp(1.0, fr == 0.5 ? ex - 1 : ex);   // smallest power of two >= mx
+    dk[t] = d;
+    if (blockIdx.x == 0) b.bscale[t] = d;
+  }
+  __syncthreads();
+  const int count = *b.count;
+  const int nvg = (count + 15) / 16;
+  double off[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const long long lim = 1ll << kCBits;
+  for (int e = blockIdx.x; e < nvg; e += kDigitBlocks) {
+    const bool in = 16 * e + c < count;
+    const int64_t j = in ? b.list[16 * e + c] : 0;
+    const double ci = in ? (double)b.cinv[j] : 0.0, mj = in ? (double)b.cm[j] : 0.0;
+    for (int r = 0; r < nrt; ++r) {
+      const int k = (t >> 4) + 16 * r;
+      const double v = in ? (double)b.beta[(int64_t)k * g.p_pad + j] * ci : 0.0;
+      long long U = llrint(v / dk[k] * (double)lim);
+      U = U > lim ? lim : (U < -lim ? -lim : U);
+      off[r] += mj * (double)U;
+      long long rest = U;
+      int8_t d[kCS];
+#pragma unroll
+      for (int sl = kCS - 1; sl > 0; --sl) {
+        const long long lo = ((rest + 64) & 127) - 64;
+        d[sl] = (int8_t)lo;
+        rest = (rest - lo) >> 7;
+      }
+      d[0] = (int8_t)rest;
+      int8_t* o = b.bd + (((int64_t)e * Kp + k) * kCS) * kGroup + c;
+#pragma unroll
+      for (int sl = 0; sl < kCS; ++sl) o[sl * kGroup] = d[sl];
+    }
+  }
+  for (int r = 0; r < nrt; ++r) {
+    double v = off[r];
+#pragma unroll
+    for (int o = 8; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    if (c == 0) b.poff[(int64_t)blockIdx.x * Kp + (t >> 4) + 16 * r] = v;
+  }
+}
+
+// The product itself.  A wavefront owns 16 RT rows and every right-hand side;
+// per 64 union columns (one MFMA K step) it loads its rows of the 64 columns
+// (lane l: column l, 16 RT contiguous bytes), transposes them
+// through LDS into the B operand (lane: row l % 16, columns 16 (l / 16) .. +15),
+// and issues RT * NRT * 4 MFMAs with the coefficient digits as the A operand,
+// so that the result lands as (right-hand side, row) with rows contiguous.
+// Splits of the union along grid.y write FP64 partials.
+constexpr int kXStride = 68;   // LDS bytes per staged column (64 rows + 4, bank spread)
+
+template <int RT, int NRT>
+__global__ __launch_bounds__(256) void k_baxpy(Geom g, BatchBufs b, int smax, int min_per) {
+  constexpr int Kp = NRT * 16;
+  __shared__ uint32_t xs[4][64 * kXStride / 4];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int count = *b.count;
+  const int nq = (count + 63) / 64;                     // 64-column K steps of the union
+  const int seff = bsplits(nq, smax, min_per);
+  const int split = blockIdx.y;
+  if (split >= seff) return;                           // uniform per block (an empty
+                                                       // union still writes split 0)
+  const int per = (nq + seff - 1) / seff;
+  const int q0 = split * per, q1 = q0 + per < nq ? q0 + per : nq;
+  const int64_t rw = ((int64_t)blockIdx.x * 4 + wv) * (16 * RT);   // first row of the wave
+  const int64_t ch = rw >> 10, roff = rw & 1023;                   // 1024-row chunks
+  v4i acc[RT][NRT][kCS];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int r = 0; r < NRT; ++r)
+#pragma unroll
+      for (int sl = 0; sl < kCS; ++sl) acc[rt][r][sl] = v4i{0, 0, 0, 0};
+  uint32_t* xw = xs[wv];
+  const int kb = lane >> 4, m = lane & 15;
+  for (int qd = q0; qd < q1; ++qd) {
+    // this lane's column: union entry 64 qd + lane (past the count it re-reads the
+    // last entry; the digits there are zero)
+    const int el = 4 * qd + kb;                           // virtual group of the A operand
+    const int il = 64 * qd + lane < count ? 64 * qd + lane : count - 1;
+    const int64_t jl = b.list[il];
+    const uint8_t* src = g.seg(jl, ch) + roff;
+    uint4 xv[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) xv[rt] = *reinterpret_cast<const uint4*>(src + 16 * rt);
+    // A operand: digits of (rhs r*16 + m, group el), 16 columns
+    v4i af[NRT][kCS];
+#pragma unroll
+    for (int r = 0; r < NRT; ++r)
+#pragma unroll
+      for (int sl = 0; sl < kCS; ++sl) {
+        if (16 * el < count) {
+          const uint4 v = *reinterpret_cast<const uint4*>(
+              b.bd + (((int64_t)el * Kp + r * 16 + m) * kCS + sl) * kGroup);
+          af[r][sl] = v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
+        } else {
+          af[r][sl] = v4i{0, 0, 0, 0};
+        }
+      }
+    // stage: column `lane` at xw[lane * kXStride / 4 ...], rows 0 .. 16 RT - 1
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      uint32_t* d = xw + lane * (kXStride / 4) + 4 * rt;
+      d[0] = xv[rt].x; d[1] = xv[rt].y; d[2] = xv[rt].z; d[3] = xv[rt].w;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const uint8_t* xb = reinterpret_cast<const uint8_t*>(xw);
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      // B operand: row 16 rt + m, columns 16 kb + 0..15
+      uint32_t w[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint8_t* p = xb + (16 * kb + 4 * q) * kXStride + 16 * rt + m;
+        w[q] = (uint32_t)p[0] | ((uint32_t)p[kXStride] << 8) | ((uint32_t)p[2 * kXStride] << 16) |
+               ((uint32_t)p[3 * kXStride] << 24);
+      }
+      const v4i bf = v4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+#pragma unroll
+      for (int r = 0; r < NRT; ++r)
+#pragma unroll
+        for (int sl = 0; sl < kCS; ++sl)
+          acc[rt][r][sl] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[r][sl], bf, acc[rt][r][sl], 0, 0, 0);
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  // lane holds C[rhs = r*16 + 4 kb + i][row = rw + 16 rt + m]
+#pragma unroll
+  for (int r = 0; r < NRT; ++r)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = r * 16 + 4 * kb + i;
+      const double unit = b.bscale[k] / (double)(1ll << kCBits);
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        long long P = 0;
+#pragma unroll
+        for (int sl = 0; sl < kCS; ++sl) P = P * 128 + (long long)acc[rt][r][sl][i];
+        b.partial[((int64_t)split * Kp + k) * g.n_pad + rw + 16 * rt + m] = (double)P * unit;
+      }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -291,10 +496,18 @@ __global__ __launch_bounds__(256) void k_bupdate(BatchBufs b, int64_t n, int64_t
   __shared__ double red[8 * 4];
   const int k = blockIdx.y;
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int seff = bsplits(*b.count, smax, min_per);
+  const int seff = bsplits((*b.count + 63) / 64, smax, min_per);
   double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  if (i < n && k < b.K) {
-    double s = b.beta0[k];
+  // mean correction of X~ B: d_k 2^-27 sum_j m_j U_kj (fixed block order)
+  __shared__ double offk;
+  if (threadIdx.x == 0) {
+    double o = 0;
+    for (int q = 0; q < kDigitBlocks; ++q) o += b.poff[(int64_t)q * Kp + k];
+    offk = o * (b.bscale[k] / (double)(1ll << kCBits));
+  }
+  __syncthreads();
+  if (i < n && k < b.K && b.kact[k]) {
+    double s = b.beta0[k] - (*b.count > 0 ? offk : 0.0);
     for (int sp = 0; sp < seff; ++sp) s += b.partial[((int64_t)sp * Kp + k) * n_pad + i];
     const int64_t o = (int64_t)k * n_pad + i;
     const float tau = b.tau[k];
@@ -354,22 +567,38 @@ hipError_t launch_batch_iteration(const Geom& g, const BatchBufs& b, int Kp, dou
   const int nrt = Kp / 16;
   hipLaunchKernelGGL(k_bdigits, dim3(nb, Kp), dim3(256), 0, s, b, g.n, g.n_pad, Kp);
   hipLaunchKernelGGL(k_bdsum, dim3(1), dim3(128), 0, s, b, (int)nb, Kp);
-  const unsigned ngb = (unsigned)((g.ngroups() + kBGroups - 1) / kBGroups);
-  switch (nrt) {
-    case 1: hipLaunchKernelGGL(k_bgemm<1>, dim3(ngb), dim3(64), 0, s, g, b, Kp); break;
-    case 2: hipLaunchKernelGGL(k_bgemm<2>, dim3(ngb), dim3(128), 0, s, g, b, Kp); break;
-    case 3: hipLaunchKernelGGL(k_bgemm<3>, dim3(ngb), dim3(192), 0, s, g, b, Kp); break;
-    case 4: hipLaunchKernelGGL(k_bgemm<4>, dim3(ngb), dim3(256), 0, s, g, b, Kp); break;
-    case 5: hipLaunchKernelGGL(k_bgemm<5>, dim3(ngb), dim3(320), 0, s, g, b, Kp); break;
-    case 6: hipLaunchKernelGGL(k_bgemm<6>, dim3(ngb), dim3(384), 0, s, g, b, Kp); break;
-    case 7: hipLaunchKernelGGL(k_bgemm<7>, dim3(ngb), dim3(448), 0, s, g, b, Kp); break;
-    case 8: hipLaunchKernelGGL(k_bgemm<8>, dim3(ngb), dim3(512), 0, s, g, b, Kp); break;
+  // one or two tiles per wavefront, GW = 4 groups (GW * TW * S * 4 <= 96 accumulators);
+  // wps = wavefronts sharing a set of groups (1, 2 or 4)
+  if (nrt == 1) {
+    const unsigned nb1 = (unsigned)((g.ngroups() + 4 * 4 - 1) / (4 * 4));
+    hipLaunchKernelGGL((k_bgemm<1, 4>), dim3(nb1), dim3(256), 0, s, g, b, Kp, 1);
+  } else {
+    const int wps = nrt <= 2 ? 1 : (nrt <= 4 ? 2 : 4);
+    const int64_t per_block = (int64_t)(4 / wps) * 4;   // groups per block (GW = 4)
+    const unsigned nbk = (unsigned)((g.ngroups() + per_block - 1) / per_block);
+    hipLaunchKernelGGL((k_bgemm<2, 4>), dim3(nbk), dim3(256), 0, s, g, b, Kp, wps);
   }
   hipLaunchKernelGGL(k_bcount, dim3(kCompactBlocks), dim3(1024), 0, s, g.ngroups(), b, nrt);
   hipLaunchKernelGGL(k_bscatter, dim3(kCompactBlocks), dim3(1024), 0, s, g.ngroups(), b, nrt,
                      eta0, Kp);
-  hipLaunchKernelGGL(k_baxpy, dim3((unsigned)((g.nchunks() + 3) / 4), smax, Kp / 4), dim3(256), 0,
-                     s, g, b, Kp, smax, min_per);
+  hipLaunchKernelGGL(k_bbmax, dim3(kDigitBlocks), dim3(256), 0, s, g, b, Kp);
+  hipLaunchKernelGGL(k_bbdigits, dim3(kDigitBlocks), dim3(256), 0, s, g, b, Kp);
+  // rows per wavefront 16 RT with RT * NRT * 16 <= 128 accumulator registers;
+  // blocks of 4 wavefronts, splits of the union along y
+  {
+    const unsigned smx = (unsigned)smax;
+    auto rows = [&](int rt) { return dim3((unsigned)(g.n_pad / (64 * rt)), smx); };
+    switch (nrt) {
+      case 1: hipLaunchKernelGGL((k_baxpy<4, 1>), rows(4), dim3(256), 0, s, g, b, smax, min_per); break;
+      case 2: hipLaunchKernelGGL((k_baxpy<2, 2>), rows(2), dim3(256), 0, s, g, b, smax, min_per); break;
+      case 3: hipLaunchKernelGGL((k_baxpy<1, 3>), rows(1), dim3(256), 0, s, g, b, smax, min_per); break;
+      case 4: hipLaunchKernelGGL((k_baxpy<1, 4>), rows(1), dim3(256), 0, s, g, b, smax, min_per); break;
+      case 5: hipLaunchKernelGGL((k_baxpy<1, 5>), rows(1), dim3(256), 0, s, g, b, smax, min_per); break;
+      case 6: hipLaunchKernelGGL((k_baxpy<1, 6>), rows(1), dim3(256), 0, s, g, b, smax, min_per); break;
+      case 7: hipLaunchKernelGGL((k_baxpy<1, 7>), rows(1), dim3(256), 0, s, g, b, smax, min_per); break;
+      case 8: hipLaunchKernelGGL((k_baxpy<1, 8>), rows(1), dim3(256), 0, s, g, b, smax, min_per); break;
+    }
+  }
   hipLaunchKernelGGL(k_bupdate, dim3(nb, Kp), dim3(256), 0, s, b, g.n, g.n_pad, Kp, mu, sigma,
                      smax, min_per);
   hipLaunchKernelGGL(k_bfinal, dim3(1), dim3(128), 0, s, b, (int)nb, Kp);
@@ -394,6 +623,32 @@ __global__ __launch_bounds__(256) void k_bzero(BatchBufs b, int64_t n_pad, int K
 
 hipError_t launch_batch_zero(const Geom& g, const BatchBufs& b, int Kp, hipStream_t s) {
   hipLaunchKernelGGL(k_bzero, dim3(64, Kp), dim3(256), 0, s, b, g.n_pad, Kp);
+  return hipGetLastError();
+}
+
+__global__ void k_zero_int(int* p) {
+  if (threadIdx.x == 0) p[0] = 0;
+}
+
+// Largest byte of the store (the matrix cores read int8 codes as signed).
+__global__ __launch_bounds__(256) void k_max_code(const uint4* __restrict__ x, int64_t n16, int* out) {
+  uint32_t mx = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += (int64_t)gridDim.x * 256) {
+    const uint4 v = x[i];
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) mx = max(mx, (w[q] >> (8 * k)) & 0xffu);
+  }
+  for (int off = 32; off >= 1; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, (int)mx);
+}
+
+hipError_t launch_max_code(const Geom& g, int* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, out);
+  hipLaunchKernelGGL(k_max_code, dim3(4096), dim3(256), 0, s,
+                     reinterpret_cast<const uint4*>(g.X), g.store_bytes() / 16, out);
   return hipGetLastError();
 }
 

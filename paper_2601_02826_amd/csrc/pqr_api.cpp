@@ -64,6 +64,7 @@ struct pqr_ctx {
   float* yb = nullptr;              // n_pad y in FP32 (batched iterations)
   float* feats = nullptr;           // p_pad x 4 features of the scoring network
   float* mlp_out = nullptr;         // p_pad x 2 network outputs
+  int max_code = -1;                // largest byte of an int8 store (-1: not measured)
 };
 
 namespace {
@@ -1160,11 +1161,18 @@ pqr_status batch_alloc(pqr_ctx* ctx, int Kp) {
   TRY(dalloc(ctx, &b.beta0, Kp * 8));
   TRY(dalloc(ctx, &b.norms, Kp * 4 * 8));
   TRY(dalloc(ctx, &b.mask, (size_t)ng * (Kp / 16) * 4));
-  TRY(dalloc(ctx, &b.list, ng * 4));
+  TRY(dalloc(ctx, &b.list, (size_t)g.p_pad * 4));
   TRY(dalloc(ctx, &b.bcnt, kCompactBlocks * 4));
   TRY(dalloc(ctx, &b.count, 64));
   TRY(dalloc(ctx, &b.partial, (size_t)smax * Kp * g.n_pad * 8));
   TRY(dalloc(ctx, &b.bpart, (size_t)nblk * Kp * 8 * 8));
+  TRY(dalloc(ctx, &b.bd, (size_t)ng * Kp * 64));
+  TRY(dalloc(ctx, &b.pmax, (size_t)256 * Kp * 8));
+  TRY(dalloc(ctx, &b.poff, (size_t)256 * Kp * 8));
+  TRY(dalloc(ctx, &b.bscale, (size_t)Kp * 8));
+  int* kact = nullptr;
+  TRY(dalloc(ctx, &kact, (size_t)Kp * 4));
+  b.kact = kact;
   b.cm = ctx->cm_f;
   b.cinv = ctx->cinv_f;
   ctx->batch_kp = Kp;
@@ -1185,6 +1193,18 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
     return PQR_ERR_INVALID_ARG;
   }
   for (int k = 0; k < K; ++k) TRY(validate_problem(ctx, y, taus[k], lambdas[k], weights));
+  if (ctx->max_code < 0) {   // the matrix cores read the int8 codes as signed
+    int* mc = nullptr;
+    TRY(dalloc(ctx, &mc, 64));
+    HIPCHK(launch_max_code(g, mc, s));
+    HIPCHK(hipMemcpyAsync(&ctx->max_code, mc, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  if (ctx->max_code > 127) {
+    ctx->err = "batched solves need int8 codes 0..127 (the store holds " +
+               std::to_string(ctx->max_code) + ")";
+    return PQR_ERR_UNSUPPORTED;
+  }
   const int Kp = (K + 15) / 16 * 16;
   TRY(batch_alloc(ctx, Kp));
   BatchBufs b = ctx->bb;
@@ -1221,6 +1241,15 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
   std::vector<char> done(K, 0);
   int64_t it = 0, certs = 0;
   int ndone = 0;
+  // convergence masks: a right-hand side whose certificate met tol_gap is frozen
+  // (its state is the certified point) and leaves the union of active columns
+  std::vector<int> kact(Kp, 0);
+  auto push_masks = [&]() -> pqr_status {
+    for (int k = 0; k < Kp; ++k) kact[k] = k < K && !done[k];
+    HIPCHK(hipMemcpyAsync(const_cast<int*>(b.kact), kact.data(), Kp * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return PQR_OK;
+  };
   // the certificate of right-hand side k reuses the single right-hand-side machinery
   auto certify = [&](int k) -> pqr_status {
     const float* bk = b.beta + (size_t)k * g.p_pad;
@@ -1247,6 +1276,7 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
     return PQR_OK;
   };
   while (ndone < K && it < ctx->opt.max_iter) {
+    TRY(push_masks());
     const int64_t chunk = std::min<int64_t>(ctx->opt.cert_every, ctx->opt.max_iter - it);
     for (int64_t q = 0; q < chunk; ++q)
       HIPCHK(launch_batch_iteration(g, b, Kp, mu, sigma, eta[0], smax, min_per, s));
@@ -1255,8 +1285,10 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
     for (int k = 0; k < K; ++k)
       if (!done[k]) TRY(certify(k));
   }
-  // final certificates of every right-hand side at the returned iterate
-  for (int k = 0; k < K; ++k) TRY(certify(k));
+  // the returned iterate of a frozen right-hand side is its certified point; the
+  // others get a final certificate of where max_iter left them
+  for (int k = 0; k < K; ++k)
+    if (!done[k]) TRY(certify(k));
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (outs) {
     std::vector<float> bf(g.p), vf(g.n);

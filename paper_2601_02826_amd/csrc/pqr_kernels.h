@@ -194,17 +194,25 @@ struct BatchBufs {
   double* scale;        // Kp digit scale c_k
   double* beta0;        // Kp
   double* norms;        // Kp x 4
-  uint32_t* mask;       // ngroups x Kp/16
-  int* list;            // ngroups
+  uint32_t* mask;       // ngroups x Kp/16 column masks (bit c: column c nonzero for a k of the tile)
+  int* list;            // p_pad: union of the nonzero columns, increasing
   int* bcnt;            // kCompactBlocks
   int* count;           // 1
   double* partial;      // smax x Kp x n_pad
   double* bpart;        // (n_pad/256) x Kp x 8
+  int8_t* bd;           // ngroups x Kp x 4 x 16: digit slices of the coefficients of
+                        // the union columns (list order), for X~ B on the matrix cores
+  double* pmax;         // 256 x Kp partial max |beta_kj / s_j|
+  double* poff;         // 256 x Kp partial sum m_j * U_kj (mean correction)
+  double* bscale;       // Kp coefficient digit scale d_k (power of two)
+  const int* kact;      // Kp: 1 = iterate right-hand side k, 0 = frozen (certified or padding)
 };
 hipError_t launch_batch_iteration(const Geom& g, const BatchBufs& b, int Kp, double mu,
                                   double sigma, double eta0, int smax, int min_per,
                                   hipStream_t s);
 hipError_t launch_batch_zero(const Geom& g, const BatchBufs& b, int Kp, hipStream_t s);
+// largest byte of the int8 store into *out (device int, set to 0 first by the launcher)
+hipError_t launch_max_code(const Geom& g, int* out, hipStream_t s);
 // flags, count and ordered list of the groups holding a nonzero of beta (b.beta);
 // b.ctl receives the count (beta0 untouched)
 template <typename T>

@@ -15,17 +15,20 @@ def _ctx(X, **kw):
                                   rows_per_lane=16, **kw)
 
 
-@pytest.mark.parametrize("K", [5, 16, 21])
-def test_batch_matches_lp_optimum(K):
+# K = 5, 16: one 16-wide tile; 21: two; 40: three (two wavefronts per group set in the
+# back-product); 128: eight (four per group set).  The LP check runs on `checked` of them.
+@pytest.mark.parametrize("K,checked", [(5, 5), (16, 16), (21, 21), (40, 8), (128, 4)])
+def test_batch_matches_lp_optimum(K, checked):
     n, p, G = 1500, 700, 3          # n pads to 2048 rows, p to 704 columns
     X, y = H.genotype_problem(n, p, seed=31)
     X1, _, _ = H.oracle_design(X, True)
     ctx = _ctx(X, G=G, tol_gap=1e-5, cert_every=200, max_iter=400_000)
-    taus = np.array([0.2, 0.5, 0.8] * 8)[:K]
-    fr = np.array([0.9, 0.6, 0.4, 0.3, 0.25, 0.2, 0.5, 0.7] * 3)[:K]
+    taus = np.resize(np.array([0.2, 0.5, 0.8]), K)
+    fr = np.resize(np.array([0.9, 0.6, 0.4, 0.3, 0.25, 0.2, 0.5, 0.7]), K)
     lams = np.array([f * pqr.lambda_max(X1, y, t) for f, t in zip(fr, taus)])
     res = ctx.solve_batch(y, taus, lams)
-    for k in range(K):
+    assert all(r["rel_gap"] <= 1e-5 for r in res)
+    for k in np.linspace(0, K - 1, checked).astype(int):
         lam_vec = H.lam_vector(p, lams[k])
         val, _ = lp.highs(X1, y, taus[k], lam_vec)
         p_gpu = pqr.objective(X1, y, res[k]["beta_std"], taus[k], lam_vec)
@@ -43,4 +46,13 @@ def test_batch_rejects_unsupported_layouts():
     with pytest.raises(pq.PQRError) as e:
         ctx.solve_batch(y, [0.5], [0.1])
     assert e.value.status == pq.PQR_ERR_UNSUPPORTED
+    ctx.close()
+    # int8 codes above 127 (read as signed by the matrix cores) are refused
+    X2 = X.astype(np.int64)
+    X2[5, 3] = 200
+    ctx = pq.Context.from_tensor(H.to_device_cols(X2.astype(np.uint8), np.uint8), store_fmt="i8",
+                                 G=2, rows_per_lane=16)
+    with pytest.raises(pq.PQRError) as e:
+        ctx.solve_batch(y, [0.5], [0.1])
+    assert e.value.status == pq.PQR_ERR_UNSUPPORTED and "127" in str(e.value)
     ctx.close()
