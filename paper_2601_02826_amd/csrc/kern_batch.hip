@@ -81,16 +81,23 @@ __global__ void k_bdsum(BatchBufs b, int nblk, int Kp) {
 // Epilogue: the weighted soft threshold of eq. beta_update for every (column,
 // k) and per (group, tile) a 16-bit mask of the columns nonzero for some k.
 // ---------------------------------------------------------------------------
-template <int TW, int GW>
+constexpr int kDRow = 128 + 16;   // LDS bytes per digit row of a 128-row tile (+16: banks)
+
+template <int TW, int GW, int DL>
 __global__ __launch_bounds__(256, 2) void k_bgemm(Geom g, BatchBufs b, int Kp, int wps) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t dtile[];   // 2 x S*Kp x kDRow
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const int nrt = Kp / 16;
   const int64_t ng = g.ngroups();
   // wps wavefronts share one set of GW groups; wavefront wv % wps takes tiles r0..
-  const int64_t gw0 = ((int64_t)blockIdx.x * (4 / wps) + wv / wps) * GW;
-  const int r0 = (wv % wps) * TW;
-  if (gw0 >= ng || r0 >= nrt) return;        // the whole wavefront (no barriers below)
+  // A wavefront past the last group or tile still runs the loop (it takes part in
+  // the digit tiles and the barriers) on clamped indices and skips the epilogue.
+  const int64_t gw0r = ((int64_t)blockIdx.x * (4 / wps) + wv / wps) * GW;
+  const int r0r = (wv % wps) * TW;
+  const bool wave_live = gw0r < ng && r0r < nrt;
+  const int64_t gw0 = gw0r < ng ? gw0r : ng - 1;
+  const int r0 = r0r < nrt ? r0r : nrt - 1;
   const int col = lane & 15, kq = lane >> 4;
   v4i acc[GW][TW][kBS];
 #pragma unroll
@@ -100,6 +107,7 @@ __global__ __launch_bounds__(256, 2) void k_bgemm(Geom g, BatchBufs b, int Kp, i
 #pragma unroll
       for (int s = 0; s < kBS; ++s) acc[q][r][s] = v4i{0, 0, 0, 0};
   const int64_t nsteps = g.nchunks() * 16;   // 64-row steps (1024-row chunks)
+  const int64_t nsup = nsteps / 2;           // 128-row digit tiles
   const bool tile_ok[2] = {true, TW > 1 && r0 + 1 < nrt};
   // Buffer loads: a lane's offset is fixed (one VGPR per fragment), the step's
   // part is a wave-uniform SGPR offset; no per-step address arithmetic.
@@ -116,18 +124,6 @@ __global__ __launch_bounds__(256, 2) void k_bgemm(Geom g, BatchBufs b, int Kp, i
 #pragma unroll
   for (int q = 0; q < GW; ++q)
     aoff[q] = (uint32_t)((gw0 + q < ng ? q : ng - 1 - gw0) * gstride + col * g.seg_bytes + kq * 16);
-  // B: digit rows (slice s, rhs (r0 + r)*16 + col), rows 16*kq .. of each step
-  // (a tile past the last one re-reads tile r0; the epilogue skips it)
-  const int64_t dbytes = (int64_t)kBS * Kp * g.n_pad;
-  const __amdgpu_buffer_rsrc_t brsrc = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)b.dig, (short)0, (int)(dbytes < 0x7fffffffll ? dbytes : 0x7fffffffll), 0x00020000);
-  uint32_t boff[TW][kBS];
-#pragma unroll
-  for (int r = 0; r < TW; ++r)
-#pragma unroll
-    for (int s = 0; s < kBS; ++s)
-      boff[r][s] = (uint32_t)(((int64_t)s * Kp + (r0 + (tile_ok[r] ? r : 0)) * 16 + col) * g.n_pad +
-                              kq * 16);
   auto load_a = [&](int64_t t, v4i (&af)[GW]) {
     const int so = (int)((t >> 4) * cstride + (t & 15) * 64);
 #pragma unroll
@@ -136,27 +132,41 @@ __global__ __launch_bounds__(256, 2) void k_bgemm(Geom g, BatchBufs b, int Kp, i
       af[q] = v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
     }
   };
-  auto load_b = [&](int64_t t, v4i (&bf)[TW][kBS]) {
-    const int so = (int)(t * 64);
+  // B: the digits of every right-hand side for 128 rows are staged once per block
+  // in LDS (row s*Kp + k: 128 bytes), double-buffered; a wavefront reads its
+  // fragments there (rhs (r0 + r)*16 + col, bytes 64 h + 16 kq of step half h).
+  const int drows = kBS * Kp, total16 = drows * 8;
+  const int64_t dbytes = (int64_t)drows * g.n_pad;
+  const __amdgpu_buffer_rsrc_t brsrc = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)b.dig, (short)0, (int)(dbytes < 0x7fffffffll ? dbytes : 0x7fffffffll), 0x00020000);
+  auto load_d = [&](int64_t u, v4u (&dr)[DL]) {
+#pragma unroll
+    for (int i = 0; i < DL; ++i) {
+      const int idx = threadIdx.x + 256 * i;
+      const int row = idx < total16 ? idx >> 3 : 0, part = idx & 7;
+      dr[i] = __builtin_amdgcn_raw_buffer_load_b128(brsrc, (int)((int64_t)row * g.n_pad + part * 16),
+                                                    (int)(u * 128), 0);
+    }
+  };
+  auto store_d = [&](int buf, const v4u (&dr)[DL]) {
+#pragma unroll
+    for (int i = 0; i < DL; ++i) {
+      const int idx = threadIdx.x + 256 * i;
+      if (idx < total16)
+        *reinterpret_cast<v4u*>(dtile + ((int64_t)buf * drows + (idx >> 3)) * kDRow + (idx & 7) * 16) =
+            dr[i];
+    }
+  };
+  auto read_b = [&](int buf, int h, v4i (&bf)[TW][kBS]) {
 #pragma unroll
     for (int r = 0; r < TW; ++r)
 #pragma unroll
       for (int s = 0; s < kBS; ++s) {
-        const v4u v = __builtin_amdgcn_raw_buffer_load_b128(brsrc, (int)boff[r][s], so, 0);
-        bf[r][s] = v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
+        const int row = s * Kp + (r0 + (tile_ok[r] ? r : 0)) * 16 + col;
+        bf[r][s] = *reinterpret_cast<const v4i*>(dtile + ((int64_t)buf * drows + row) * kDRow +
+                                                 h * 64 + kq * 16);
       }
   };
-  // Two fragment sets in ping-pong (the step count is even: 16 per chunk): a
-  // set is reloaded for the step after next right after its MFMAs issue, so
-  // the other set's loads are in flight while these MFMAs run and no register
-  // is copied.  Loads past the end re-read the last step (in bounds).
-  v4i aS[2][GW], bS[2][TW][kBS];
-  load_b(0, bS[0]);
-  load_a(0, aS[0]);
-  __builtin_amdgcn_sched_barrier(0);   // set 0 strictly older than set 1 on entry
-  load_b(1, bS[1]);
-  load_a(1, aS[1]);
-  __builtin_amdgcn_sched_barrier(0);
   auto mma = [&](const v4i (&af)[GW], const v4i (&bf)[TW][kBS]) {
 #pragma unroll
     for (int q = 0; q < GW; ++q)
@@ -166,20 +176,40 @@ __global__ __launch_bounds__(256, 2) void k_bgemm(Geom g, BatchBufs b, int Kp, i
         for (int s = 0; s < kBS; ++s)
           acc[q][r][s] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[q], bf[r][s], acc[q][r][s], 0, 0, 0);
   };
-  // (scheduling barriers keep each set's reload between the two MFMA phases)
-  for (int64_t t = 0; t < nsteps; t += 2) {
-    mma(aS[0], bS[0]);
+  // Two A fragment sets in ping-pong (steps 2u and 2u + 1 of digit tile u): a set
+  // is reloaded for the next tile right after its MFMAs issue, so the other set's
+  // loads are in flight while these MFMAs run.  The next digit tile is loaded at
+  // the top of a tile and stored to the other LDS buffer at its end; one barrier
+  // per tile.  Scheduling barriers keep this order; loads past the end re-read
+  // the last tile (in bounds).
+  v4i aS[2][GW], bf[TW][kBS];
+  v4u dr[DL];
+  load_d(0, dr);
+  store_d(0, dr);
+  __syncthreads();
+  load_a(0, aS[0]);
+  __builtin_amdgcn_sched_barrier(0);   // set 0 strictly older than set 1 on entry
+  load_a(1, aS[1]);
+  __builtin_amdgcn_sched_barrier(0);
+  for (int64_t u = 0; u < nsup; ++u) {
+    const int buf = (int)(u & 1);
+    load_d(u + 1 < nsup ? u + 1 : u, dr);
     __builtin_amdgcn_sched_barrier(0);
-    const int64_t t2 = t + 2 < nsteps ? t + 2 : nsteps - 2;
-    load_b(t2, bS[0]);
+    read_b(buf, 0, bf);
+    mma(aS[0], bf);
+    __builtin_amdgcn_sched_barrier(0);
+    const int64_t t2 = 2 * u + 2 < nsteps ? 2 * u + 2 : nsteps - 2;
     load_a(t2, aS[0]);
     __builtin_amdgcn_sched_barrier(0);
-    mma(aS[1], bS[1]);
+    read_b(buf, 1, bf);
+    mma(aS[1], bf);
     __builtin_amdgcn_sched_barrier(0);
-    load_b(t2 + 1, bS[1]);
     load_a(t2 + 1, aS[1]);
     __builtin_amdgcn_sched_barrier(0);
+    store_d(buf ^ 1, dr);
+    __syncthreads();
   }
+  if (!wave_live) return;
   // epilogue: lane holds columns 4*kq + e (e = 0..3) of each group for rhs (r0+r)*16 + col
 #pragma unroll
   for (int r = 0; r < TW; ++r) {
@@ -568,15 +598,31 @@ hipError_t launch_batch_iteration(const Geom& g, const BatchBufs& b, int Kp, dou
   hipLaunchKernelGGL(k_bdigits, dim3(nb, Kp), dim3(256), 0, s, b, g.n, g.n_pad, Kp);
   hipLaunchKernelGGL(k_bdsum, dim3(1), dim3(128), 0, s, b, (int)nb, Kp);
   // one or two tiles per wavefront, GW = 4 groups (GW * TW * S * 4 <= 96 accumulators);
-  // wps = wavefronts sharing a set of groups (1, 2 or 4)
-  if (nrt == 1) {
-    const unsigned nb1 = (unsigned)((g.ngroups() + 4 * 4 - 1) / (4 * 4));
-    hipLaunchKernelGGL((k_bgemm<1, 4>), dim3(nb1), dim3(256), 0, s, g, b, Kp, 1);
-  } else {
+  // wps = wavefronts sharing a set of groups (1, 2 or 4); LDS: two digit tiles
+  {
+    const size_t lds = (size_t)2 * kBS * Kp * kDRow;
     const int wps = nrt <= 2 ? 1 : (nrt <= 4 ? 2 : 4);
     const int64_t per_block = (int64_t)(4 / wps) * 4;   // groups per block (GW = 4)
-    const unsigned nbk = (unsigned)((g.ngroups() + per_block - 1) / per_block);
-    hipLaunchKernelGGL((k_bgemm<2, 4>), dim3(nbk), dim3(256), 0, s, g, b, Kp, wps);
+    const dim3 grid((unsigned)((g.ngroups() + per_block - 1) / per_block));
+    auto go = [&](auto kern) {
+      static bool attr_set = false;   // more than 64 KB of dynamic LDS needs the attribute
+      if (!attr_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr_set = true;
+      }
+      hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, g, b, Kp, wps);
+    };
+    switch (nrt) {   // DL = ceil(24 Kp / 256) digit loads per thread and tile
+      case 1: go(k_bgemm<1, 4, 2>); break;
+      case 2: go(k_bgemm<2, 4, 3>); break;
+      case 3: go(k_bgemm<2, 4, 5>); break;
+      case 4: go(k_bgemm<2, 4, 6>); break;
+      case 5: go(k_bgemm<2, 4, 8>); break;
+      case 6: go(k_bgemm<2, 4, 9>); break;
+      case 7: go(k_bgemm<2, 4, 11>); break;
+      case 8: go(k_bgemm<2, 4, 12>); break;
+    }
   }
   hipLaunchKernelGGL(k_bcount, dim3(kCompactBlocks), dim3(1024), 0, s, g.ngroups(), b, nrt);
   hipLaunchKernelGGL(k_bscatter, dim3(kCompactBlocks), dim3(1024), 0, s, g.ngroups(), b, nrt,
