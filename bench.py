@@ -13,6 +13,17 @@ solve, X-passes/s, the live roofline of the sweep kernel (HIP events on the
 solver's stream) and the oracle timed on the host cores.
 
     python bench.py [--steps K] [--warmup W] [--fmt i8|2bit|fp8|bf16] [--tol 1e-3]
+
+Other workloads (one JSON line each, same keys):
+
+    --workload batched   the same design, a 3 x 7 grid (tau in {0.1, 0.5, 0.9},
+                         lambda / lambda_max(tau) in {0.7, 0.5, 0.4, 0.3, 0.2, 0.15, 0.1})
+                         solved as 21 right-hand sides of one batched solve on the int8
+                         matrix cores; the plain path (warm-started per tau) is timed
+                         once after the timed steps for the speedup.
+    --workload grouped   64 independent uneven genotype problems (n ~ U[500, 5000],
+                         p ~ U[10k, 200k], 18.8 G entries) solved by one grouped solve;
+                         one-by-one solves are timed once after the timed steps.
 """
 import argparse
 import hashlib
@@ -32,6 +43,9 @@ BYTES_PER = {"i8": 1.0, "fp8": 1.0, "2bit": 0.25, "bf16": 2.0, "f32": 4.0}
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="path", choices=["path", "batched", "grouped"])
+    ap.add_argument("--skip-reference", action="store_true",
+                    help="batched/grouped: skip the plain / one-by-one comparison run")
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--fmt", default="i8", choices=sorted(BYTES_PER))
@@ -54,24 +68,39 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def source_hash():
+def source_hash(files=("kern_iter.hip", "pqr_dev.h")):
     h = hashlib.sha256()
-    for f in ("kern_iter.hip", "pqr_dev.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2601_02826_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(fmt, n, p):
-    """HBM bytes per sweep launch from the committed rocprofv3 --pmc summary,
-    if it was taken on the current sweep kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"sweep_{fmt}_{n // 1000}kx{p // 1000}k_traffic.json")
+def traffic_from_profile(name, files=("kern_iter.hip", "pqr_dev.h")):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary
+    profiles/<name>_traffic.json, if it was taken on the current kernel source;
+    else None."""
+    path = os.path.join(ROOT, "profiles", f"{name}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("kernel_source_sha") != source_hash():
+    if rec.get("kernel_source_sha") != source_hash(files):
         return None
     return rec.get("traffic_bytes_per_launch")
+
+
+def calibrate_copy(mib):
+    """One plain device copy of `mib` MiB (a kernel of known size for scaling the
+    HBM byte counters of a --pmc run)."""
+    if mib <= 0:
+        return
+    import torch
+    src = torch.ones(mib << 20, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def make_workload(n, p):
@@ -148,6 +177,10 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
+    if a.workload == "batched":
+        return bench_batched(a)
+    if a.workload == "grouped":
+        return bench_grouped(a)
     import numpy as np
     import torch
     import paper_2601_02826_amd as pq
@@ -166,13 +199,7 @@ def main():
     y = g["y"]
     lmax = ctx.lambda_max(y, 0.5)
     lams = lmax * 0.01 ** (np.arange(a.npath) / 19.0)
-    if a.calibrate_copy > 0:
-        src = torch.ones(a.calibrate_copy << 20, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    calibrate_copy(a.calibrate_copy)
 
     for w in range(a.warmup):
         run_path(ctx, y, lams)
@@ -231,7 +258,7 @@ def main():
         "setup_s": setup_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic_from_profile(a.fmt, n, p),
+                     "traffic": traffic_from_profile(f"sweep_{a.fmt}_{n // 1000}kx{p // 1000}k"),
                      "kernel": "k_sweep (X~^T theta + weighted soft threshold)",
                      "kernel_avg_ms": sweep_avg_ms, "launches": launches,
                      "algorithmic_bytes_per_launch": alg_bytes},
@@ -239,6 +266,207 @@ def main():
     }
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+MFMA_INT8_PEAK_TOPS = 5000.0
+GRID_TAUS = (0.1, 0.5, 0.9)
+GRID_FRACS = (0.7, 0.5, 0.4, 0.3, 0.2, 0.15, 0.1)
+
+
+def bench_batched(a):
+    """21 (tau, lambda) right-hand sides on the 20k x 1M int8 design in one batched solve."""
+    import numpy as np
+    import torch
+    import paper_2601_02826_amd as pq
+    spec, g, Xc = make_workload(a.n, a.p)
+    t0 = time.perf_counter()
+    ctx = pq.Context.from_tensor(Xc, store_fmt="i8", standardize=True, G=a.G, tol_gap=a.tol,
+                                 cert_every=a.cert_every, max_iter=a.max_iter * 4, profile=1)
+    ctx._keep = None
+    del Xc
+    torch.cuda.empty_cache()
+    setup_s = time.perf_counter() - t0
+    y = g["y"]
+    taus, lams, groups = [], [], []
+    for t in GRID_TAUS:
+        lm = ctx.lambda_max(y, t)
+        ll = [f * lm for f in GRID_FRACS]
+        taus += [t] * len(ll)
+        lams += ll
+        groups.append((t, ll))
+    K = len(taus)
+    calibrate_copy(a.calibrate_copy)
+    for w in range(a.warmup):
+        ctx.solve_batch(y, taus, lams, allow_not_converged=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = []
+    for k in range(a.steps):
+        res = ctx.solve_batch(y, taus, lams, allow_not_converged=True)
+        runs.append(res)
+        log(f"step {k + 1}/{a.steps}: {res[0]['iters']} iterations, {res[0]['certs']} certificates, "
+            f"max gap {max(r['rel_gap'] for r in res):.2e}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    res = runs[-1]
+    conv = sum(r["status"] == 0 for r in res)
+    # the plain path on the same 21 problems (warm starts along each tau's lambdas)
+    t0 = time.perf_counter()
+    plain_iters, plain_conv = 0, 0
+    for t, ll in ([] if a.skip_reference else groups):
+        for k, lam in enumerate(ll):
+            r = ctx.solve(y, t, lam, start="zero" if k == 0 else "device", allow_not_converged=True)
+            plain_iters += r["iters"]
+            plain_conv += r["status"] == 0
+    plain_s = time.perf_counter() - t0 if not a.skip_reference else None
+    Kp = (K + 15) // 16 * 16
+    n, p = a.n, a.p
+    n_pad, p_pad = (n + 1023) // 1024 * 1024, (p + 15) // 16 * 16
+    gemm_avg_ms = res[0]["sweep_ms"] / max(1, res[0]["sweep_launches"])
+    alg_bytes = n * p + 3 * Kp * n + 8 * Kp * p + 12 * p
+    achieved = alg_bytes / (gemm_avg_ms * 1e-3) / 1e9
+    tops = 2.0 * n_pad * p_pad * Kp * 3 / (gemm_avg_ms * 1e-3) / 1e12
+    cpu = None
+    if a.cpu_cols > 0:
+        try:
+            cpu = cpu_baseline(spec, g, a.cpu_cols, max(plain_iters, res[0]["iters"]) / K, p)
+        except Exception as e:  # noqa: BLE001
+            log(f"cpu baseline failed: {e}")
+    out = {
+        "metric": METRIC,
+        "value": K * a.steps / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": elapsed / a.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "i8 mfma (exact digit slices) + f32 iterates", "data": "synthetic",
+        "config": {"workload": f"batched: genotype n={n} p={p} int8, tau in {list(GRID_TAUS)} x "
+                               f"lambda/lambda_max in {list(GRID_FRACS)} = {K} right-hand sides in one "
+                               f"batched solve, certified rel. duality gap <= {a.tol:g}",
+                   "n": n, "p": p, "right_hand_sides": K, "tol_gap": a.tol, "blocks": a.G,
+                   "parallelism": "single GPU"},
+        "time_to_kkt_s_all": elapsed / a.steps,
+        "solves_converged": f"{conv}/{K}",
+        "iterations": res[0]["iters"],
+        "certificates": res[0]["certs"],
+        "plain_path_s": plain_s, "plain_iterations": plain_iters,
+        "plain_converged": f"{plain_conv}/{K}",
+        "speedup_vs_plain": plain_s / (elapsed / a.steps) if plain_s else None,
+        "setup_s": setup_s,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic_from_profile(f"bgemm_i8_{n // 1000}kx{p // 1000}k_k{K}",
+                                                     ("kern_batch.hip",)),
+                     "kernel": "k_bgemm (X~^T Theta on int8 MFMA + weighted soft threshold)",
+                     "kernel_avg_ms": gemm_avg_ms, "launches": res[0]["sweep_launches"],
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "mfma_tops": tops, "mfma_peak_tops": MFMA_INT8_PEAK_TOPS,
+                     "mfma_frac": tops / MFMA_INT8_PEAK_TOPS},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def bench_grouped(a):
+    """64 independent uneven genotype problems in one grouped solve."""
+    import numpy as np
+    import torch
+    import paper_2601_02826_amd as pq
+    from datagen import native
+    from datagen.configs import grouped_specs, make_genotype
+    specs = grouped_specs(64)
+    ctxs, ys, taus, lams = [], [], [], []
+    t0 = time.perf_counter()
+    entries = 0
+    for spec, lf in specs:
+        gi = make_genotype(spec, with_X=False)
+        thr = torch.from_numpy(gi["thr"].astype(np.int64)).to(torch.int32).cuda()
+        Xc = torch.empty((spec.p, spec.n), dtype=torch.uint8, device="cuda")
+        native.genotype_device(Xc.data_ptr(), spec.n, spec.n, spec.p, thr.data_ptr(), spec.seed,
+                               spec.tag, torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        ctx = pq.Context.from_tensor(Xc, store_fmt="i8", G=a.G, tol_gap=a.tol,
+                                     cert_every=a.cert_every, max_iter=a.max_iter * 30, profile=1)
+        ctx._keep = None
+        del Xc
+        ctxs.append(ctx)
+        ys.append(gi["y"])
+        taus.append(spec.tau)
+        lams.append(lf * ctx.lambda_max(gi["y"], spec.tau))
+        entries += spec.n * spec.p
+    torch.cuda.empty_cache()
+    setup_s = time.perf_counter() - t0
+    log(f"64 problems set up in {setup_s:.1f}s ({entries / 1e9:.2f} G entries)")
+    calibrate_copy(a.calibrate_copy)
+    for w in range(a.warmup):
+        pq.solve_grouped(ctxs, ys, taus, lams, allow_not_converged=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        res, sts = pq.solve_grouped(ctxs, ys, taus, lams, allow_not_converged=True)
+        its = [r["iters"] for r in res]
+        log(f"step {k + 1}/{a.steps}: iterations min/median/max {min(its)}/{int(np.median(its))}/"
+            f"{max(its)}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    conv = sum(st == pq.PQR_OK for st in sts)
+    seq_s, same = None, None
+    if not a.skip_reference:
+        t0 = time.perf_counter()
+        seq = [ctxs[i].solve(ys[i], taus[i], lams[i], allow_not_converged=True) for i in range(64)]
+        seq_s = time.perf_counter() - t0
+        same = all(np.array_equal(seq[i]["beta_std"], res[i]["beta_std"]) for i in range(64))
+    # algorithmic bytes of all grouped sweeps: problem i's design once per iteration
+    alg_total = sum(float(s.n * s.p + 4 * s.n + 20 * s.p) * r["iters"]
+                    for (s, _), r in zip(specs, res))
+    sweep_ms = res[0]["sweep_ms"]
+    launches = res[0]["sweep_launches"]
+    achieved = alg_total / (sweep_ms * 1e-3) / 1e9
+    cpu = None
+    if a.cpu_cols > 0:
+        try:
+            spec0 = specs[0][0]
+            g0 = make_genotype(spec0, with_X=False)
+            one = cpu_baseline(spec0, g0, min(a.cpu_cols, spec0.p), 1.0, spec0.p)
+            per_entry_iter = one["sec_per_iteration_full"] / (spec0.n * spec0.p)
+            work = sum(float(s.n * s.p) * r["iters"] for (s, _), r in zip(specs, res))
+            cpu = dict(value=64.0 / (per_entry_iter * work), unit="problems/s", cores=one["cores"],
+                       kind="oracle",
+                       sample=(one["sample"].split(", per-iteration")[0] + f" of problem 0 "
+                               f"(n={spec0.n}); time per iteration and entry, scaled by the GPU's "
+                               f"iterations x entries summed over the 64 problems"))
+        except Exception as e:  # noqa: BLE001
+            log(f"cpu baseline failed: {e}")
+    out = {
+        "metric": METRIC,
+        "value": 64 * a.steps / elapsed,
+        "unit": "problems/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": elapsed / a.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"grouped: 64 independent genotype problems, n ~ U[500,5000], "
+                               f"p ~ U[10k,200k] ({entries / 1e9:.2f} G int8 entries), tau_i in 0.1..0.9, "
+                               f"lambda_i / lambda_max,i ~ U(0.2, 0.6), one grouped solve, certified "
+                               f"rel. duality gap <= {a.tol:g}",
+                   "problems": 64, "entries": entries, "tol_gap": a.tol, "blocks": a.G,
+                   "parallelism": "single GPU"},
+        "solves_converged": f"{conv}/64",
+        "one_by_one_s": seq_s,
+        "speedup_vs_one_by_one": seq_s / (elapsed / a.steps) if seq_s else None,
+        "identical_to_one_by_one": same,
+        "setup_s": setup_s,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_gsweep (grouped X~^T theta + soft threshold, all problems)",
+                     "kernel_avg_ms": sweep_ms / max(1, launches), "launches": launches,
+                     "algorithmic_bytes_per_launch": alg_total / max(1, launches)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    for c in ctxs:
+        c.close()
 
 
 if __name__ == "__main__":

@@ -118,7 +118,8 @@ typedef struct {
   double lambda_max;    /* smallest lambda with the null fit optimal (same tau, weights) */
   double mu;            /* the mu used                                          */
   double seconds;       /* wall time of the call                                */
-  double sweep_ms;      /* with opt.profile: summed duration of the sweep kernels  */
+  double sweep_ms;      /* with opt.profile: summed duration of the sweep kernels
+                           (pqr_solve_batch: of the batched back-product kernel)  */
   int64_t sweep_launches;
 } pqr_result;
 

@@ -269,7 +269,8 @@ class Context:
             o = outs[k]
             res.append(Result(**keep[k], iters=o.iters, x_passes=o.x_passes, certs=o.certs,
                               nnz=o.nnz, primal=o.primal, dual=o.dual, rel_gap=o.rel_gap,
-                              mu=o.mu, seconds=o.seconds, status=st))
+                              mu=o.mu, seconds=o.seconds, sweep_ms=o.sweep_ms,
+                              sweep_launches=o.sweep_launches, status=st))
         return res
 
     def kkt_columns(self, y, tau, lam, beta_std, theta, weights=None):

@@ -591,7 +591,7 @@ __global__ void k_bfinal(BatchBufs b, int nblk, int Kp) {
 // ---------------------------------------------------------------------------
 hipError_t launch_batch_iteration(const Geom& g, const BatchBufs& b, int Kp, double mu,
                                   double sigma, double eta0, int smax, int min_per,
-                                  hipStream_t s) {
+                                  hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (g.fmt != I8 || g.rpl != 16 || Kp % 16 || Kp > 128) return hipErrorInvalidValue;
   const unsigned nb = (unsigned)(g.n_pad / 256);
   const int nrt = Kp / 16;
@@ -611,7 +611,9 @@ hipError_t launch_batch_iteration(const Geom& g, const BatchBufs& b, int Kp, dou
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr_set = true;
       }
+      if (ev0) (void)hipEventRecord(ev0, s);
       hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, g, b, Kp, wps);
+      if (ev1) (void)hipEventRecord(ev1, s);
     };
     switch (nrt) {   // DL = ceil(24 Kp / 256) digit loads per thread and tile
       case 1: go(k_bgemm<1, 4, 2>); break;

@@ -857,21 +857,24 @@ pqr_status grouped_impl(int nprob, pqr_ctx* const* ctxs, const double* const* ys
     if (st[i] != PQR_OK) runs[i].status = st[i];
   }
   const bool prof = c0->opt.profile != 0;
-  // device table and events, released on every exit path
+  // device table, released on every exit path
   struct Owned {
     GroupDesc<T>* desc = nullptr;
     int* off = nullptr;
-    hipEvent_t ev[2] = {nullptr, nullptr};
     ~Owned() {
       if (desc) (void)hipFree(desc);
       if (off) (void)hipFree(off);
-      for (auto& e : ev)
-        if (e) (void)hipEventDestroy(e);
     }
   } own;
-  hipEvent_t* ev = own.ev;
-  if (prof)
-    for (int k = 0; k < 2; ++k) HIPCHK(hipEventCreate(&ev[k]));
+  if (prof) {   // two events per iteration of a chunk, on the first context
+    int64_t cmax = 1;
+    for (int i = 0; i < nprob; ++i) cmax = std::max<int64_t>(cmax, ctxs[i]->opt.cert_every);
+    if (c0->events.size() < 2 * (size_t)cmax) {
+      const size_t old = c0->events.size();
+      c0->events.resize(2 * (size_t)cmax);
+      for (size_t e = old; e < c0->events.size(); ++e) HIPCHK(hipEventCreate(&c0->events[e]));
+    }
+  }
   double sweep_ms = 0.0;
   int64_t sweeps = 0;
   pqr_status fail = PQR_OK;
@@ -918,19 +921,19 @@ pqr_status grouped_impl(int nprob, pqr_ctx* const* ctxs, const double* const* ys
     if (fail != PQR_OK) break;
     HIPCHK(hipMemcpyAsync(desc_d, desc.data(), sizeof(GroupDesc<T>) * na, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(off_d, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice, s));
-    for (int64_t k = 0; k < chunk; ++k) {
-      const bool rec = prof && k == 0;
-      HIPCHK(launch_grouped_iteration<T>(c0->g, desc_d, off_d, na, tot, s, rec ? ev[0] : nullptr,
-                                         rec ? ev[1] : nullptr));
-      if (rec) {
-        HIPCHK(hipStreamSynchronize(s));
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
-        sweep_ms += ms * (double)chunk;   // the first launch of a chunk stands for the chunk
-        sweeps += chunk;
-      }
-    }
+    for (int64_t k = 0; k < chunk; ++k)
+      HIPCHK(launch_grouped_iteration<T>(c0->g, desc_d, off_d, na, tot, s,
+                                         prof ? c0->events[2 * k] : nullptr,
+                                         prof ? c0->events[2 * k + 1] : nullptr));
     HIPCHK(hipStreamSynchronize(s));
+    if (prof) {
+      for (int64_t k = 0; k < chunk; ++k) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, c0->events[2 * k], c0->events[2 * k + 1]));
+        sweep_ms += ms;
+      }
+      sweeps += chunk;
+    }
     for (int i : act) {
       st[i] = runs[i].after_chunk(chunk);
       if (st[i] != PQR_OK) runs[i].status = st[i];
@@ -1275,13 +1278,31 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
     if (rel[k] <= ctx->opt.tol_gap && !done[k]) { done[k] = 1; ++ndone; }
     return PQR_OK;
   };
+  const bool prof = ctx->opt.profile != 0;
+  if (prof && ctx->events.size() < 2 * (size_t)ctx->opt.cert_every) {
+    const size_t old = ctx->events.size();
+    ctx->events.resize(2 * (size_t)ctx->opt.cert_every);
+    for (size_t e = old; e < ctx->events.size(); ++e) HIPCHK(hipEventCreate(&ctx->events[e]));
+  }
+  double gemm_ms = 0.0;
+  int64_t gemm_launches = 0;
   while (ndone < K && it < ctx->opt.max_iter) {
     TRY(push_masks());
     const int64_t chunk = std::min<int64_t>(ctx->opt.cert_every, ctx->opt.max_iter - it);
     for (int64_t q = 0; q < chunk; ++q)
-      HIPCHK(launch_batch_iteration(g, b, Kp, mu, sigma, eta[0], smax, min_per, s));
+      HIPCHK(launch_batch_iteration(g, b, Kp, mu, sigma, eta[0], smax, min_per, s,
+                                    prof ? ctx->events[2 * q] : nullptr,
+                                    prof ? ctx->events[2 * q + 1] : nullptr));
     it += chunk;
     HIPCHK(hipStreamSynchronize(s));
+    if (prof) {
+      for (int64_t q = 0; q < chunk; ++q) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ctx->events[2 * q], ctx->events[2 * q + 1]));
+        gemm_ms += ms;
+      }
+      gemm_launches += chunk;
+    }
     for (int k = 0; k < K; ++k)
       if (!done[k]) TRY(certify(k));
   }
@@ -1334,8 +1355,8 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
       o->lambda_max = 0.0;
       o->mu = mu;
       o->seconds = secs;
-      o->sweep_ms = 0.0;
-      o->sweep_launches = 0;
+      o->sweep_ms = gemm_ms;             // with opt.profile: the back-product kernel
+      o->sweep_launches = gemm_launches;
     }
   }
   if (ndone < K) {

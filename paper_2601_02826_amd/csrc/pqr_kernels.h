@@ -207,9 +207,11 @@ struct BatchBufs {
   double* bscale;       // Kp coefficient digit scale d_k (power of two)
   const int* kact;      // Kp: 1 = iterate right-hand side k, 0 = frozen (certified or padding)
 };
+// One batched iteration; with non-null events, ev0/ev1 are recorded around the
+// back-product kernel (k_bgemm).
 hipError_t launch_batch_iteration(const Geom& g, const BatchBufs& b, int Kp, double mu,
                                   double sigma, double eta0, int smax, int min_per,
-                                  hipStream_t s);
+                                  hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_batch_zero(const Geom& g, const BatchBufs& b, int Kp, hipStream_t s);
 // largest byte of the int8 store into *out (device int, set to 0 first by the launcher)
 hipError_t launch_max_code(const Geom& g, int* out, hipStream_t s);
