@@ -269,19 +269,26 @@ typedef struct {
   int64_t active_final;     /* columns of the last reduced problem                  */
   int64_t reduced_iters;    /* iterations spent in reduced solves                   */
   double seconds_proposal, seconds_reduced, seconds_check;   /* cumulative          */
+  /* with ctx's profile option: the reduced solves' sweep kernels, their summed
+     duration, launches and algorithmic bytes (n |A| b + 4n + 20|A| per launch)   */
+  double reduced_sweep_ms, reduced_sweep_bytes;
+  int64_t reduced_sweep_launches;
 } pqr_learned_report;
 
 /* Learned warm start: the network (params, device) proposes coefficients and an
- * active set A = {j : o1_j > threshold} plus the 32 columns with the largest o1;
- * FS-QRPPA solves the problem restricted to
- * A (to tol_gap/4) from that proposal (beta_0 = the tau-quantile of y, z = y -
- * beta_0, theta = the null-fit dual); the FP64 certificate on the full design then
- * judges it.  If its gap exceeds tol_gap, the columns outside A whose
- * |x~_j^T theta'| exceeds lambda_j (1 + 1e-6) join A, or, when there are none, the
- * reduced solve is repeated 4x tighter, from the previous solution (at most
- * max_rounds reduced solves).  If no round passes, the plain FS-QRPPA solve from a
- * zero start on the full design gives the answer (rep->fallback = 1).  The
- * reported rel_gap is always the full design's certificate. */
+ * active set A = {j : o1_j > threshold} plus the 32 columns with the largest o1.
+ * FS-QRPPA solves the problem restricted to A from that proposal (beta_j =
+ * o0_j sd(y) on A, beta_0 = the tau-quantile of y, z = y - X~beta - beta_0 and
+ * theta_i = (tau - 1{z_i < 0}) / n centred, as PQR_START_HOST with only beta);
+ * the FP64 certificate on the full design then judges the result.  The first
+ * round stops at 10 tol_gap when more rounds are allowed (enough to expose
+ * violators), later rounds at tol_gap.  If the full gap exceeds tol_gap, the
+ * columns outside A whose |x~_j^T theta'| exceeds lambda_j (1 + 1e-6) join A and
+ * the next round starts from the previous solution; with no violator the next
+ * round is solved 4x tighter (at most max_rounds reduced solves).  If no round
+ * passes, the plain FS-QRPPA solve from a zero start on the full design gives the
+ * answer (rep->fallback = 1).  The reported rel_gap is always the full design's
+ * certificate. */
 pqr_status pqr_solve_learned(pqr_ctx* ctx, const double* y, double tau, double lambda,
                              const double* weights, const float* params, double threshold,
                              int max_rounds, pqr_result* out, pqr_learned_report* rep);

@@ -57,7 +57,9 @@ class pqr_learned_report(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int), ("fallback", ctypes.c_int),
                 ("active_initial", ctypes.c_int64), ("active_final", ctypes.c_int64),
                 ("reduced_iters", ctypes.c_int64), ("seconds_proposal", ctypes.c_double),
-                ("seconds_reduced", ctypes.c_double), ("seconds_check", ctypes.c_double)]
+                ("seconds_reduced", ctypes.c_double), ("seconds_check", ctypes.c_double),
+                ("reduced_sweep_ms", ctypes.c_double), ("reduced_sweep_bytes", ctypes.c_double),
+                ("reduced_sweep_launches", ctypes.c_int64)]
 
 _lib = None
 
@@ -327,7 +329,10 @@ class Context:
                       lambda_max=out.lambda_max, seconds=out.seconds, status=st,
                       rounds=rep.rounds, fallback=rep.fallback, active_initial=rep.active_initial,
                       active_final=rep.active_final, reduced_iters=rep.reduced_iters,
-                      seconds_proposal=rep.seconds_proposal)
+                      seconds_proposal=rep.seconds_proposal, seconds_reduced=rep.seconds_reduced,
+                      seconds_check=rep.seconds_check, reduced_sweep_ms=rep.reduced_sweep_ms,
+                      reduced_sweep_bytes=rep.reduced_sweep_bytes,
+                      reduced_sweep_launches=rep.reduced_sweep_launches)
 
     def kkt(self, y, tau, lam, beta_std, theta, weights=None):
         rep = np.zeros(4)

@@ -1530,8 +1530,7 @@ extern "C" pqr_status pqr_solve_learned(pqr_ctx* ctx, const double* y, double ta
   for (int round = 0; round < max_rounds && !A.empty(); ++round) {
     ++r.rounds;
     pqr_ctx* sub = nullptr;
-    pqr_options so = ctx->opt;
-    so.profile = 0;
+    pqr_options so = ctx->opt;   // the parent's profile option carries over
     so.tol_gap = sub_tol;
     so.G = (int)std::max<int64_t>(1, std::min<int64_t>(ctx->Gf, ((int64_t)A.size() + 15) / 16));
     pqr_status st = pqr_create_subset(&sub, ctx, A.data(), (int64_t)A.size(), &so);
@@ -1561,6 +1560,11 @@ extern "C" pqr_status pqr_solve_learned(pqr_ctx* ctx, const double* y, double ta
     st = pqr_solve(sub, y, tau, lambda, weights ? wl.data() : nullptr, PQR_START_HOST, &warm, &res);
     iters += res.iters;
     r.reduced_iters += res.iters;
+    r.reduced_sweep_ms += res.sweep_ms;
+    r.reduced_sweep_launches += res.sweep_launches;
+    r.reduced_sweep_bytes += (double)res.sweep_launches *
+                             ((double)g.n * (double)A.size() * (fmt_col_bytes(g.fmt, 1024) / 1024.0) +
+                              4.0 * (double)g.n + 20.0 * (double)A.size());
     pqr_destroy(sub);
     if (st != PQR_OK && st != PQR_ERR_NOT_CONVERGED) return st;
     // embed and check on the full design: FP64 certificate and every column's dual value
