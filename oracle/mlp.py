@@ -8,7 +8,8 @@ column being active.  The loss per row is
     w_reg (o0 - t)^2 + w_pos a softplus(-o1) + (1 - a) softplus(o1),
 
 averaged over the rows, with target coefficient t and activity a in {0, 1}.
-Parity: pinned by central differences (tests/test_oracle_mlp.py).
+Parity: pinned by central differences and a hand-written closed form
+(tests/test_oracle_pins.py).
 """
 import numpy as np
 

@@ -53,24 +53,6 @@ def test_mlp_forward_and_gradient_vs_oracle(B):
     assert float(loss.item()) == pytest.approx(lw, rel=1e-5)
 
 
-def test_mlp_oracle_central_differences():
-    """The FP64 oracle's gradient itself against central differences (pins O10)."""
-    rng = np.random.default_rng(3)
-    prm = omlp.init_params(1)
-    F = rng.standard_normal((17, 4))
-    t = rng.standard_normal(17) * 0.2
-    a = (rng.random(17) < 0.3).astype(float)
-    g = omlp.flatten(omlp.backward(prm, F, t, a, w_reg=2.0, w_pos=3.0))
-    flat = omlp.flatten(prm)
-    h = 1e-6
-    for q in rng.choice(flat.size, 60, replace=False):
-        e = np.zeros_like(flat)
-        e[q] = h
-        fd = (omlp.loss(omlp.unflatten(flat + e), F, t, a, 2.0, 3.0) -
-              omlp.loss(omlp.unflatten(flat - e), F, t, a, 2.0, 3.0)) / (2 * h)
-        assert abs(fd - g[q]) <= 1e-7 * max(1.0, abs(g[q]))
-
-
 def test_adam_step():
     import torch
     import paper_2601_02826_amd as pq

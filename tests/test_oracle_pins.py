@@ -343,3 +343,43 @@ def test_standardize_and_back_transform():
     bs[1 + 3] = 0
     b = pqr.back_transform(bs, m, s)
     assert np.allclose(pqr.with_intercept(Xt) @ bs, pqr.with_intercept(X) @ b)
+
+
+# ---- the scoring network of the learned warm start (oracle/mlp.py) ----
+def test_mlp_oracle_gradient_central_differences():
+    """The FP64 oracle's backward pass against central differences of its loss, on
+    every parameter block (a dropped term or transposed weight shows up here)."""
+    from oracle import mlp as omlp
+    rng = np.random.default_rng(3)
+    prm = omlp.init_params(1)
+    F = rng.standard_normal((17, 4))
+    t = rng.standard_normal(17) * 0.2
+    a = (rng.random(17) < 0.3).astype(float)
+    g = omlp.flatten(omlp.backward(prm, F, t, a, w_reg=2.0, w_pos=3.0))
+    flat = omlp.flatten(prm)
+    h = 1e-6
+    picks = np.concatenate([rng.choice(flat.size, 60, replace=False),
+                            np.cumsum([0] + [int(np.prod(omlp.SHAPES[k])) for k in omlp.ORDER])[:-1]])
+    for q in picks:
+        e = np.zeros_like(flat)
+        e[q] = h
+        fd = (omlp.loss(omlp.unflatten(flat + e), F, t, a, 2.0, 3.0) -
+              omlp.loss(omlp.unflatten(flat - e), F, t, a, 2.0, 3.0)) / (2 * h)
+        assert abs(fd - g[q]) <= 1e-7 * max(1.0, abs(g[q]))
+
+
+def test_mlp_oracle_forward_closed_form():
+    """With one hidden unit active per layer the network is a closed-form scalar
+    chain: out = W3 silu(W2 silu(W1 f + b1) + b2) + b3, written out by hand."""
+    from oracle import mlp as omlp
+    prm = {k: np.zeros_like(v) for k, v in omlp.init_params(0).items()}
+    names = list(prm)
+    W1, b1, W2, b2, W3, b3 = (prm[k] for k in names)
+    W1[0, 2] = 0.5; b1[0] = -0.1
+    W2[3, 0] = 2.0; b2[3] = 0.25
+    W3[0, 3] = -1.5; W3[1, 3] = 0.75; b3[:] = [0.2, -0.3]
+    f = np.array([[0.0, 0.0, 1.2, 0.0]])
+    sil = lambda x: x / (1 + np.exp(-x))
+    h2 = sil(2.0 * sil(0.5 * 1.2 - 0.1) + 0.25)
+    out, _ = omlp.forward(prm, f)
+    assert np.allclose(out[0], [-1.5 * h2 + 0.2, 0.75 * h2 - 0.3], rtol=1e-14, atol=1e-15)
