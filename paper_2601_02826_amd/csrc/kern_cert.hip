@@ -122,6 +122,74 @@ static void dots64_fmt(const Geom& g, const double* tp, const double* sum_tp, co
                      s, g, tp, sum_tp, cm, cinv, clam, v, gmax);
 }
 
+// Up to four certificates at once (int8 store, 16 rows per lane: the batched
+// layout): v_kj = x~_j^T theta'_k in FP64 for k < kb (theta'_k at tp + k n_pad,
+// sum theta'_k at out + 8k + 5), one pass over X; per group and k the max
+// |v_kj| / (lam_k w_j) into gmax[k * ngroups + grp].  A lane keeps the raw bytes
+// of its 16 rows of the 16 columns and walks them four rows at a time, with the
+// four theta' slices of those rows in registers.
+struct Lam4 { double v[4]; };
+
+__global__ __launch_bounds__(256) void k_mdots64(Geom g, const double* __restrict__ tp, int kb,
+                                                 const double* out, const double* __restrict__ cm,
+                                                 const double* __restrict__ cinv,
+                                                 const double* __restrict__ w, Lam4 lam,
+                                                 double* gmax) {
+  const int lane = threadIdx.x & 63;
+  const int64_t grp = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t ng = g.ngroups();
+  if (grp >= ng) return;
+  double acc[kGroup][4];
+#pragma unroll
+  for (int c = 0; c < kGroup; ++c)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[c][k] = 0;
+  const int64_t nch = g.nchunks();
+  for (int64_t ch = 0; ch < nch; ++ch) {
+    const int64_t row0 = ch * (kWave * 16) + (int64_t)lane * 16;
+    const uint8_t* base = g.seg(grp * kGroup, ch) + lane * 16;
+    uint4 raw[kGroup];
+#pragma unroll
+    for (int c = 0; c < kGroup; ++c) raw[c] = *reinterpret_cast<const uint4*>(base + c * g.seg_bytes);
+#pragma unroll
+    for (int r4 = 0; r4 < 4; ++r4) {
+      double th[4][4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          th[k][r] = k < kb ? tp[(int64_t)k * g.n_pad + row0 + 4 * r4 + r] : 0.0;
+#pragma unroll
+      for (int c = 0; c < kGroup; ++c) {
+        const uint32_t wd = r4 == 0 ? raw[c].x : (r4 == 1 ? raw[c].y : (r4 == 2 ? raw[c].z : raw[c].w));
+        double x[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[r] = (double)((wd >> (8 * r)) & 0xffu);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[c][k] = fma(x[r], th[k][r], acc[c][k]);
+      }
+    }
+  }
+  const int64_t j = grp * kGroup + group_col_of_lane(lane);
+  const bool owner = (lane & 3) == 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (k >= kb) break;
+    double a[kGroup];
+#pragma unroll
+    for (int c = 0; c < kGroup; ++c) a[c] = acc[c][k];
+    const double dot = reduce16(a, lane);
+    const double vj = (dot - cm[j] * out[8 * k + 5]) * cinv[j];
+    const double lj = lam.v[k] * w[j];
+    double ratio = 0.0;
+    if (cinv[j] != 0.0) ratio = lj > 0.0 ? fabs(vj) / lj : (vj != 0.0 ? INFINITY : 0.0);
+    ratio = wave_max(owner ? ratio : 0.0);
+    if (lane == 0) gmax[(int64_t)k * ng + grp] = ratio;
+  }
+}
+
 #define PQR_DISPATCH64(FN, ...)                                          \
   switch (g.fmt * 2 + (g.rpl == 16)) {                                   \
     case F64 * 2: FN<F64, 4>(__VA_ARGS__); break;                        \
@@ -137,6 +205,17 @@ static void dots64_fmt(const Geom& g, const double* tp, const double* sum_tp, co
     case B2 * 2 + 1: FN<B2, 16>(__VA_ARGS__); break;                     \
     default: return hipErrorInvalidValue;                                \
   }
+
+hipError_t launch_mdots64(const Geom& g, const double* tp, int kb, const double* out,
+                          const double* cm, const double* cinv, const double* w,
+                          const double* lam, double* gmax, hipStream_t s) {
+  if (kb < 1 || kb > 4 || g.fmt != I8 || g.rpl != 16) return hipErrorInvalidValue;
+  Lam4 l4{{0, 0, 0, 0}};
+  for (int k = 0; k < kb; ++k) l4.v[k] = lam[k];
+  hipLaunchKernelGGL(k_mdots64, dim3((unsigned)((g.ngroups() + 3) / 4)), dim3(256), 0, s, g, tp, kb,
+                     out, cm, cinv, w, l4, gmax);
+  return hipGetLastError();
+}
 
 hipError_t launch_dots64(const Geom& g, const double* theta_p, const double* sum_tp,
                          const double* cm, const double* cinv, const double* clam, double* v,

@@ -64,6 +64,9 @@ struct pqr_ctx {
   float* yb = nullptr;              // n_pad y in FP32 (batched iterations)
   float* feats = nullptr;           // p_pad x 4 features of the scoring network
   float* mlp_out = nullptr;         // p_pad x 2 network outputs
+  double* cert4 = nullptr;          // 4 x n_pad projected thetas (batched certificates)
+  double* out4 = nullptr;           // 4 x 8 certificate outputs
+  double* gmax4 = nullptr;          // 4 x ngroups dual-ratio partials
   int max_code = -1;                // largest byte of an int8 store (-1: not measured)
 };
 
@@ -1176,6 +1179,11 @@ pqr_status batch_alloc(pqr_ctx* ctx, int Kp) {
   int* kact = nullptr;
   TRY(dalloc(ctx, &kact, (size_t)Kp * 4));
   b.kact = kact;
+  if (!ctx->cert4) {
+    TRY(dalloc(ctx, &ctx->cert4, (size_t)4 * g.n_pad * 8));
+    TRY(dalloc(ctx, &ctx->out4, 32 * 8));
+    TRY(dalloc(ctx, &ctx->gmax4, (size_t)4 * ng * 8));
+  }
   b.cm = ctx->cm_f;
   b.cinv = ctx->cinv_f;
   ctx->batch_kp = Kp;
@@ -1253,30 +1261,77 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
     HIPCHK(hipStreamSynchronize(s));
     return PQR_OK;
   };
-  // the certificate of right-hand side k reuses the single right-hand-side machinery
-  auto certify = [&](int k) -> pqr_status {
-    const float* bk = b.beta + (size_t)k * g.p_pad;
-    const float* tk = b.theta + (size_t)k * g.n_pad;
-    double b0 = 0.0;
-    HIPCHK(hipMemcpyAsync(&b0, b.beta0 + k, 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    Ctl c;
-    std::memset(&c, 0, sizeof(c));
-    c.beta0 = b0;
-    HIPCHK(hipMemcpyAsync(ctx->ctl_kkt, &c, sizeof(Ctl), hipMemcpyHostToDevice, s));
-    IterBufs<float> v = bufs<float>(ctx);
-    v.beta = const_cast<float*>(bk);
-    v.ctl = ctx->ctl_kkt;
-    HIPCHK(launch_active_list<float>(g, v, s));
-    HIPCHK(launch_scale(ctx->w_d, lambdas[k], g.p_pad, ctx->clam_d, s));
-    Cert cert{};
-    TRY(certify_point<float>(ctx, taus[k], tk, bk, ctx->ctl_kkt, ctx->list, &cert));
-    ++certs;
-    best_dual[k] = std::max(best_dual[k], cert.dual);
-    primal[k] = cert.primal;
-    rel[k] = (primal[k] - best_dual[k]) / std::max(std::fabs(primal[k]), 1e-300);
-    if (rel[k] <= ctx->opt.tol_gap && !done[k]) { done[k] = 1; ++ndone; }
+  // FP64 certificates of the right-hand sides in `ks`, four at a time: the
+  // projections per k, one shared pass over X for the dual ratios (the dense
+  // part), then the sparse primal per k.  Same arithmetic as pqr_kkt.
+  std::vector<double> bout(32);
+  auto certify_many = [&](const std::vector<int>& ks) -> pqr_status {
+    for (size_t c0 = 0; c0 < ks.size(); c0 += 4) {
+      const int kb = (int)std::min<size_t>(4, ks.size() - c0);
+      double lam4[4] = {0, 0, 0, 0};
+      for (int i = 0; i < kb; ++i) {
+        const int k = ks[c0 + i];
+        lam4[i] = lambdas[k];
+        HIPCHK(launch_project<float>(b.theta + (size_t)k * g.n_pad, g.n, g.n_pad, taus[k], ctx->y_d,
+                                     ctx->cert4 + (size_t)i * g.n_pad, ctx->out4 + 8 * i, s));
+      }
+      HIPCHK(launch_mdots64(g, ctx->cert4, kb, ctx->out4, ctx->cm_d, ctx->cinv_d, ctx->w_d, lam4,
+                            ctx->gmax4, s));
+      for (int i = 0; i < kb; ++i)
+        HIPCHK(launch_reduce_max(ctx->gmax4 + (size_t)i * ng, ng, ctx->bpart64,
+                                 ctx->out4 + 8 * i + 3, s));
+      for (int i = 0; i < kb; ++i) {
+        const int k = ks[c0 + i];
+        const float* bk = b.beta + (size_t)k * g.p_pad;
+        double b0 = 0.0;
+        HIPCHK(hipMemcpyAsync(&b0, b.beta0 + k, 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        Ctl c;
+        std::memset(&c, 0, sizeof(c));
+        c.beta0 = b0;
+        HIPCHK(hipMemcpyAsync(ctx->ctl_kkt, &c, sizeof(Ctl), hipMemcpyHostToDevice, s));
+        IterBufs<float> v = bufs<float>(ctx);
+        v.beta = const_cast<float*>(bk);
+        v.ctl = ctx->ctl_kkt;
+        HIPCHK(launch_active_list<float>(g, v, s));
+        HIPCHK(launch_scale(ctx->w_d, lambdas[k], g.p_pad, ctx->clam_d, s));
+        HIPCHK(launch_to_double<float>(bk, g.p_pad, ctx->beta_d, s));
+        CertBufs cb{};
+        cb.y = ctx->y_d;
+        cb.theta_p = ctx->cert4 + (size_t)i * g.n_pad;
+        cb.beta_d = ctx->beta_d;
+        cb.cm = ctx->cm_d;
+        cb.cinv = ctx->cinv_d;
+        cb.clam = ctx->clam_d;
+        cb.partial = ctx->partial64;
+        cb.list = ctx->list;
+        cb.ctl = ctx->ctl_kkt;
+        cb.bpart = ctx->bpart64;
+        cb.out = ctx->out4 + 8 * i;
+        HIPCHK(launch_primal64(g, cb, taus[k], ctx->smax, ctx->min_per, s));
+      }
+      HIPCHK(hipMemcpyAsync(bout.data(), ctx->out4, 32 * 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      for (int i = 0; i < kb; ++i) {
+        const int k = ks[c0 + i];
+        const double* o = bout.data() + 8 * i;
+        const double mr = o[3];
+        const double alpha = mr > 1.0 ? (std::isinf(mr) ? 0.0 : 1.0 / mr) : 1.0;
+        ++certs;
+        best_dual[k] = std::max(best_dual[k], alpha * o[2]);
+        primal[k] = o[0] + o[1];
+        rel[k] = (primal[k] - best_dual[k]) / std::max(std::fabs(primal[k]), 1e-300);
+      }
+    }
+    for (int k : ks)
+      if (rel[k] <= ctx->opt.tol_gap && !done[k]) { done[k] = 1; ++ndone; }
     return PQR_OK;
+  };
+  auto pending = [&]() {
+    std::vector<int> ks;
+    for (int k = 0; k < K; ++k)
+      if (!done[k]) ks.push_back(k);
+    return ks;
   };
   const bool prof = ctx->opt.profile != 0;
   if (prof && ctx->events.size() < 2 * (size_t)ctx->opt.cert_every) {
@@ -1303,13 +1358,11 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
       }
       gemm_launches += chunk;
     }
-    for (int k = 0; k < K; ++k)
-      if (!done[k]) TRY(certify(k));
+    TRY(certify_many(pending()));
   }
   // the returned iterate of a frozen right-hand side is its certified point; the
-  // others get a final certificate of where max_iter left them
-  for (int k = 0; k < K; ++k)
-    if (!done[k]) TRY(certify(k));
+  // others were certified where max_iter left them (max_iter = 0: certify now)
+  if (it == 0) TRY(certify_many(pending()));
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (outs) {
     std::vector<float> bf(g.p), vf(g.n);

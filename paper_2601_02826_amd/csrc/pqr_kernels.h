@@ -119,6 +119,15 @@ hipError_t launch_dots64(const Geom& g, const double* theta_p, const double* sum
                          const double* cm, const double* cinv, const double* clam, double* v,
                          double* gmax, hipStream_t s);
 
+// Up to four certificates in one pass (int8 store, rows_per_lane 16): for k < kb
+// (<= 4) the per-group max of
+// |x~_j^T theta'_k| / (lam[k] w_j) into gmax[k * ngroups + grp], with theta'_k at
+// tp + k n_pad and sum(theta'_k) at out[8k + 5] (launch_project's layout); lam
+// is host, kb doubles.
+hipError_t launch_mdots64(const Geom& g, const double* tp, int kb, const double* out,
+                          const double* cm, const double* cinv, const double* w,
+                          const double* lam, double* gmax, hipStream_t s);
+
 // Sparse s = X~ beta over the active list in FP64, then P(beta) pieces.
 hipError_t launch_primal64(const Geom& g, const CertBufs& c, double tau, int smax, int min_per,
                            hipStream_t s);
