@@ -4,15 +4,20 @@
 plain FP64 oracle.
 
 One step = the whole hot path over the workload: the 20-point lambda path
-lambda_t = lambda_max * 0.01^((t-1)/19), t = 1..20, at tau = 0.5, each point
-solved by FS-QRPPA to a certified relative duality gap <= --tol and warm-started
-from the previous point on the device (set-up, i.e. encoding, column statistics
-and the Lanczos step sizes, happens once before timing).  `value` is solves per
-second (20 solves per step); the JSON line also carries the time-to-KKT per
-solve, X-passes/s, the live roofline of the sweep kernel (HIP events on the
-solver's stream) and the oracle timed on the host cores.
+lambda_t = lambda_max * 0.01^((t-1)/19), t = 1..20, at tau = 0.5, every point
+solved by FS-QRPPA to a certified relative duality gap <= --tol (set-up, i.e.
+encoding, column statistics and the Lanczos step sizes, happens once before
+timing).  By default (--mode batched, int8 store) the 20 points are the 20
+right-hand sides of one batched solve on the int8 matrix cores; --mode
+sequential solves them one after another, each warm-started from the previous
+point on the device, and is also run once after the timed steps of the batched
+mode for comparison.  `value` is solves per second (20 solves per step); the
+JSON line also carries the time-to-KKT per solve, the live roofline of the
+dominant kernel (HIP events on the solver's stream) and the oracle timed on the
+host cores.
 
-    python bench.py [--steps K] [--warmup W] [--fmt i8|2bit|fp8|bf16] [--tol 1e-3]
+    python bench.py [--steps K] [--warmup W] [--mode batched|sequential]
+                    [--fmt i8|2bit|fp8|bf16] [--tol 1e-3]
 
 Other workloads (one JSON line each, same keys):
 
@@ -49,6 +54,9 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="path", choices=["path", "batched", "grouped", "learned"])
+    ap.add_argument("--mode", default="batched", choices=["batched", "sequential"],
+                    help="path workload: one batched solve of the 20 points, or warm-started "
+                         "solves one after another (other store formats than int8: sequential)")
     ap.add_argument("--train-problems", type=int, default=4,
                     help="learned: generated 5000 x 100k problems the network is trained on")
     ap.add_argument("--skip-reference", action="store_true",
@@ -190,6 +198,8 @@ def main():
         return bench_grouped(a)
     if a.workload == "learned":
         return bench_learned(a)
+    if a.mode == "batched" and a.fmt == "i8":
+        return bench_path_batched(a)
     import numpy as np
     import torch
     import paper_2601_02826_amd as pq
@@ -271,6 +281,107 @@ def main():
                      "kernel": "k_sweep (X~^T theta + weighted soft threshold)",
                      "kernel_avg_ms": sweep_avg_ms, "launches": launches,
                      "algorithmic_bytes_per_launch": alg_bytes},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def bench_path_batched(a):
+    """The headline path as 20 right-hand sides of one batched solve."""
+    import numpy as np
+    import torch
+    import paper_2601_02826_amd as pq
+    t0 = time.perf_counter()
+    spec, g, Xc = make_workload(a.n, a.p)
+    log(f"workload generated in {time.perf_counter() - t0:.1f}s")
+    t0 = time.perf_counter()
+    ctx = pq.Context.from_tensor(Xc, store_fmt="i8", standardize=True, G=a.G, tol_gap=a.tol,
+                                 cert_every=a.cert_every, max_iter=a.max_iter * 4, profile=1)
+    ctx._keep = None
+    del Xc
+    torch.cuda.empty_cache()
+    setup_s = time.perf_counter() - t0
+    log(f"setup (encode, column statistics, Lanczos step sizes) {setup_s:.2f}s")
+    y = g["y"]
+    lmax = ctx.lambda_max(y, 0.5)
+    lams = lmax * 0.01 ** (np.arange(a.npath) / 19.0)
+    taus = np.full(a.npath, 0.5)
+    calibrate_copy(a.calibrate_copy)
+    for w in range(a.warmup):
+        ctx.solve_batch(y, taus, lams, allow_not_converged=True)
+        log(f"warmup step {w + 1}/{a.warmup} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        res = ctx.solve_batch(y, taus, lams, allow_not_converged=True)
+        log(f"step {k + 1}/{a.steps}: {res[0]['iters']} iterations, {res[0]['certs']} certificates, "
+            f"gaps " + " ".join(f"{r['rel_gap']:.1e}" for r in res))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    solves = a.npath * a.steps
+    conv = sum(r["status"] == 0 for r in res)
+    n, p = a.n, a.p
+    Kp = (a.npath + 15) // 16 * 16
+    n_pad, p_pad = (n + 1023) // 1024 * 1024, (p + 15) // 16 * 16
+    gemm_avg_ms = res[0]["sweep_ms"] / max(1, res[0]["sweep_launches"])
+    alg_bytes = n * p + 3 * Kp * n + 8 * Kp * p + 12 * p
+    achieved = alg_bytes / (gemm_avg_ms * 1e-3) / 1e9
+    tops = 2.0 * n_pad * p_pad * Kp * 3 / (gemm_avg_ms * 1e-3) / 1e12
+    seq = None
+    seq_iters = None
+    if not a.skip_reference:
+        t1 = time.perf_counter()
+        recs = run_path(ctx, y, lams)
+        seq_s = time.perf_counter() - t1
+        seq_iters = sum(r["iters"] for r in recs)
+        sw_ms = sum(r["sweep_ms"] for r in recs) / max(1, sum(r["sweep_launches"] for r in recs))
+        sw_bytes = n * p + 4 * n + 20 * p
+        seq = {"mode": "sequential, warm starts on the device", "seconds": seq_s,
+               "solves_per_s": a.npath / seq_s,
+               "solves_converged": f"{sum(r['status'] == 0 for r in recs)}/{a.npath}",
+               "iterations_per_solve": seq_iters / a.npath,
+               "sweep": {"kernel": "k_sweep", "kernel_avg_ms": sw_ms,
+                         "achieved_GBs": sw_bytes / (sw_ms * 1e-3) / 1e9,
+                         "frac": sw_bytes / (sw_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "traffic": traffic_from_profile(f"sweep_i8_{n // 1000}kx{p // 1000}k"),
+                         "algorithmic_bytes_per_launch": sw_bytes}}
+    cpu = None
+    if a.cpu_cols > 0:
+        try:
+            per = (seq_iters / a.npath) if seq_iters else res[0]["iters"]
+            cpu = cpu_baseline(spec, g, a.cpu_cols, per, p)
+        except Exception as e:  # noqa: BLE001
+            log(f"cpu baseline failed: {e}")
+    out = {
+        "metric": METRIC,
+        "value": solves / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": elapsed / a.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "i8 mfma (exact digit slices) + f32 iterates", "data": "synthetic",
+        "config": {"workload": f"genotype lambda path, n={n} p={p} X i8, tau=0.5, {a.npath} lambdas "
+                               f"lambda_max..0.01 lambda_max as {a.npath} right-hand sides of one "
+                               f"batched solve, certified rel. duality gap <= {a.tol:g}",
+                   "n": n, "p": p, "x_format": "i8", "tau": 0.5, "path_points": a.npath,
+                   "tol_gap": a.tol, "blocks": a.G, "mode": "batched",
+                   "parallelism": "single GPU"},
+        "time_to_kkt_s_per_solve": elapsed / solves,
+        "solves_converged": f"{conv}/{a.npath}",
+        "iterations": res[0]["iters"], "certificates": res[0]["certs"],
+        "setup_s": setup_s,
+        "sequential_reference": seq,
+        "speedup_vs_sequential": (seq["seconds"] / (elapsed / a.steps)) if seq else None,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic_from_profile(f"bgemm_i8_{n // 1000}kx{p // 1000}k_kp{Kp}",
+                                                     ("kern_batch.hip",)),
+                     "kernel": "k_bgemm (X~^T Theta on int8 MFMA + weighted soft threshold)",
+                     "kernel_avg_ms": gemm_avg_ms, "launches": res[0]["sweep_launches"],
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "mfma_tops": tops, "mfma_peak_tops": MFMA_INT8_PEAK_TOPS,
+                     "mfma_frac": tops / MFMA_INT8_PEAK_TOPS},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -364,7 +475,7 @@ def bench_batched(a):
         "setup_s": setup_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic_from_profile(f"bgemm_i8_{n // 1000}kx{p // 1000}k_k{K}",
+                     "traffic": traffic_from_profile(f"bgemm_i8_{n // 1000}kx{p // 1000}k_kp{Kp}",
                                                      ("kern_batch.hip",)),
                      "kernel": "k_bgemm (X~^T Theta on int8 MFMA + weighted soft threshold)",
                      "kernel_avg_ms": gemm_avg_ms, "launches": res[0]["sweep_launches"],
