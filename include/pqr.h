@@ -160,7 +160,11 @@ pqr_status pqr_solve(pqr_ctx* ctx, const double* y, double tau, double lambda,
  * solver's scale; theta: host n doubles.  Pure: no state changes.
  * rep[0] = primal P(beta), rep[1] = dual objective of the projected theta,
  * rep[2] = relative gap, rep[3] = max_j |x~_j^T theta'| / lambda_j over
- * penalized columns (<= 1 means dual feasible before scaling). */
+ * penalized columns (<= 1 means dual feasible before scaling).  Columns with
+ * weight 0 are unpenalized: theta' is first projected onto {sum theta = 0,
+ * x~_j^T theta = 0 on them} and scaled back into the box (at most 4096 such
+ * columns; the equalities hold to rounding, like sum theta = 0 for the
+ * intercept). */
 pqr_status pqr_kkt(pqr_ctx* ctx, const double* y, double tau, double lambda,
                    const double* weights, const double* beta_std, const double* theta,
                    double rep[4]);
@@ -187,12 +191,32 @@ pqr_status pqr_iterate(pqr_ctx* ctx, const double* y, double tau, double lambda,
                        const double* weights, double mu, const double* eta, int64_t iters,
                        double* beta_std, double* z, double* theta);
 
+/* Folded-concave penalties by L-step local linear approximation (Algorithm 2):
+ * stage 0 is pqr_solve at unit weights from a zero start; stage l = 1..L solves
+ * the weighted problem with lambda_j = lambda w_j, w_j = max(p'_lambda(|b_j|) /
+ * lambda, wfloor), b the previous stage's coefficients on the standardized scale
+ * and p' the SCAD derivative (eq. scad, penalty 0, a > 2) or the MCP derivative
+ * (eq. mcp, penalty 1, a > 1), warm-started on the device from the previous stage
+ * (PQR_START_DEVICE).  Zero weights (SCAD beyond a lambda, MCP beyond a lambda)
+ * make columns unpenalized; the certificate then projects its dual point onto
+ * x~_j^T theta = 0 for them (see pqr_kkt), so wfloor = 0 runs Algorithm 2 exactly;
+ * a positive floor changes a stage's objective by at most wfloor lambda sum_j |b_j|
+ * over the floored columns.
+ *  weights_out  NULL or host, p+1 doubles: the last stage's weights (w_0 = 0)
+ *  stage_iters  NULL or host, L+1 iteration counts
+ *  out          the last stage's result (as pqr_solve)
+ * Stops at the first stage that does not return PQR_OK and returns its status. */
+pqr_status pqr_solve_lla(pqr_ctx* ctx, const double* y, double tau, double lambda,
+                         int penalty, double a, int L, double wfloor, double* weights_out,
+                         int64_t* stage_iters, pqr_result* out);
+
 /* K problems that share X, y and the weights, with their own (tau_k, lambda_k),
  * solved together (Algorithm 1 for every k, iterated in lockstep).  The back-
  * products X~^T Theta of all k run on the int8 matrix cores over digit slices of
  * theta (exact integer arithmetic); every k is stopped by its own FP64 duality-gap
- * certificate (pqr_kkt's).  Needs an int8 store, rows_per_lane 16 and FP32
- * iterates (PQR_ERR_UNSUPPORTED otherwise); 1 <= K <= 128.
+ * certificate (pqr_kkt's).  Needs an int8 store with codes 0..127, rows_per_lane
+ * 16, FP32 iterates and positive weights (PQR_ERR_UNSUPPORTED otherwise);
+ * 1 <= K <= 128.
  *  y, weights  as in pqr_solve;  taus, lambdas  host, K doubles each
  *  outs        host array of K pqr_result (output arrays optional, as in pqr_solve);
  *              beta/z/theta are the final iterate, rel_gap its certified gap

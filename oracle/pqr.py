@@ -247,17 +247,33 @@ def project_box_sum(theta, lo, hi, iters=200):
 def dual_certificate(X1, y, tau, lam, beta, theta):
     """Weak-duality certificate.  The dual of the constrained form is
     max_theta y^T theta  s.t.  (tau-1)/n <= theta_i <= tau/n,  |x_j^T theta| <= lam_j
-    (lam_0 = 0 forces sum theta = 0).  theta is made feasible by a shift-and-clip
-    projection and a scaling alpha in (0, 1]; gap = P(beta) - y^T theta~ >= 0."""
+    (lam_0 = 0 forces sum theta = 0, and any other lam_j = 0 forces x_j^T theta = 0).
+    theta is made feasible by a shift-and-clip projection; with unpenalized feature
+    columns U it is then projected onto {sum theta = 0, X_U^T theta = 0} (least
+    squares) and scaled toward 0, which lies inside the box, until the box holds;
+    finally a scaling alpha in (0, 1] meets |x_j^T theta| <= lam_j.  The equality
+    constraints hold to rounding.  gap = P(beta) - y^T theta~ >= 0."""
     n = X1.shape[0]
     lo, hi = (tau - 1.0) / n, tau / n
     tp = project_box_sum(theta, lo, hi)
-    v = X1[:, 1:].T @ tp
     lj = lam[1:]
+    U = np.nonzero(lj == 0)[0]
+    if len(U):
+        A = np.column_stack([np.ones(n), X1[:, 1 + U]])
+        c, *_ = np.linalg.lstsq(A, tp, rcond=None)
+        t1 = tp - A @ c
+        s = 1.0
+        for t in t1:
+            if t > hi:
+                s = min(s, hi / t)
+            elif t < lo:
+                s = min(s, lo / t)
+        tp = s * t1
+    v = X1[:, 1:].T @ tp
     alpha = 1.0
     for vj, l in zip(np.abs(v), lj):
-        if vj > l:
-            alpha = min(alpha, l / vj if vj > 0 else 1.0)
+        if l > 0 and vj > l:
+            alpha = min(alpha, l / vj)
     tf = alpha * tp
     primal = objective(X1, y, beta, tau, lam)
     dual = _sum(y * tf)

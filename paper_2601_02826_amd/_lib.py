@@ -49,7 +49,7 @@ class pqr_result(ctypes.Structure):
 SYMBOLS = ["pqr_default_options", "pqr_create", "pqr_solve", "pqr_kkt", "pqr_lambda_max",
            "pqr_blocks", "pqr_iterate", "pqr_solve_batch", "pqr_kkt_columns", "pqr_create_subset",
            "pqr_mlp_param_count", "pqr_features", "pqr_mlp_forward", "pqr_mlp_workspace_bytes",
-           "pqr_mlp_grad", "pqr_mlp_adam", "pqr_solve_learned", "pqr_solve_grouped",
+           "pqr_mlp_grad", "pqr_mlp_adam", "pqr_solve_learned", "pqr_solve_grouped", "pqr_solve_lla",
            "pqr_destroy", "pqr_last_error", "pqr_status_string"]
 
 
@@ -116,6 +116,9 @@ def load():
                                       ctypes.POINTER(_c_dp), ctypes.POINTER(pqr_result),
                                       ctypes.POINTER(ci)]
     lib.pqr_solve_grouped.restype = ci
+    lib.pqr_solve_lla.argtypes = [vp, _c_dp, dbl, dbl, ci, dbl, ci, dbl, _c_dp,
+                                  ctypes.POINTER(i64), ctypes.POINTER(pqr_result)]
+    lib.pqr_solve_lla.restype = ci
     lib.pqr_destroy.argtypes = [vp]
     lib.pqr_destroy.restype = None
     lib.pqr_last_error.argtypes = [vp]
@@ -333,6 +336,28 @@ class Context:
                       seconds_check=rep.seconds_check, reduced_sweep_ms=rep.reduced_sweep_ms,
                       reduced_sweep_bytes=rep.reduced_sweep_bytes,
                       reduced_sweep_launches=rep.reduced_sweep_launches)
+
+    def solve_lla(self, y, tau, lam, penalty="scad", a=None, L=1, wfloor=0.0,
+                  allow_not_converged=False):
+        """pqr_solve_lla (Algorithm 2).  Returns the last stage's Result with extra keys
+        `weights` (p+1) and `stage_iters` (L+1)."""
+        kind = {"scad": 0, "mcp": 1}[penalty]
+        if a is None:
+            a = 3.7 if kind == 0 else 3.0
+        beta = np.zeros(self.p + 1)
+        beta_std = np.zeros(self.p + 1)
+        z = np.zeros(self.n)
+        theta = np.zeros(self.n)
+        w = np.zeros(self.p + 1)
+        its = (ctypes.c_int64 * (L + 1))()
+        out = pqr_result(beta=_dptr(beta), beta_std=_dptr(beta_std), z=_dptr(z), theta=_dptr(theta))
+        st = self._lib.pqr_solve_lla(self._h, _dptr(_f64(y, self.n)), float(tau), float(lam), kind,
+                                     float(a), int(L), float(wfloor), _dptr(w), its, ctypes.byref(out))
+        ok = (PQR_OK, PQR_ERR_NOT_CONVERGED) if allow_not_converged else (PQR_OK,)
+        self._check(st, ok)
+        return Result(beta=beta, beta_std=beta_std, z=z, theta=theta, iters=out.iters,
+                      nnz=out.nnz, primal=out.primal, dual=out.dual, rel_gap=out.rel_gap,
+                      seconds=out.seconds, status=st, weights=w, stage_iters=list(its))
 
     def kkt(self, y, tau, lam, beta_std, theta, weights=None):
         rep = np.zeros(4)

@@ -107,8 +107,10 @@ __global__ __launch_bounds__(256) void k_dots64(Geom g, const double* __restrict
   const bool owner = (lane & 3) == 0;
   const double vj = (dot - cm[j] * sum_tp[0]) * cinv[j];
   const double lam = clam[j];
+  // lambda_j = 0 (an unpenalized column) is enforced by the projection onto
+  // x~_j^T theta = 0 before this pass (launch_unpen_*), not by the ratio
   double ratio = 0.0;
-  if (cinv[j] != 0.0) ratio = lam > 0.0 ? fabs(vj) / lam : (vj != 0.0 ? INFINITY : 0.0);
+  if (cinv[j] != 0.0 && lam > 0.0) ratio = fabs(vj) / lam;
   if (owner && v) v[j] = vj;
   ratio = wave_max(owner ? ratio : 0.0);
   if (lane == 0) gmax[grp] = ratio;
@@ -362,6 +364,150 @@ __global__ __launch_bounds__(256) void k_scale(const double* w, double a, int64_
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256)
     out[i] = a * w[i];
 }
+
+// ---------------------------------------------------------------------------
+// Unpenalized columns U (lambda_j = 0) in the dual certificate: the dual point
+// must satisfy x~_j^T theta = 0 for j in U, besides sum theta = 0 (the
+// intercept).  theta' (box-feasible, sum zero) is projected onto that subspace,
+// theta1 = theta' - A c with A = [1, X~_U] and (A^T A) c = A^T theta', then scaled
+// toward 0 (strictly inside the box) until the box holds.
+// ---------------------------------------------------------------------------
+// Dense x~ of the columns cols[0..nu) (nu x n_pad, zero on padding rows); a
+// column index -1 stands for the intercept (ones on the n rows).
+template <int FMT, int RPL>
+__global__ __launch_bounds__(64) void k_dense_cols(Geom g, const int64_t* cols,
+                                                   const double* cm, const double* cinv,
+                                                   double* xu) {
+  const int64_t c = blockIdx.y, ch = blockIdx.x;
+  const int64_t j = cols[c];
+  const int lane = threadIdx.x;
+  const int64_t row0 = ch * (kWave * RPL) + (int64_t)lane * RPL;
+  if (j < 0) {
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) xu[c * g.n_pad + row0 + r] = row0 + r < g.n ? 1.0 : 0.0;
+    return;
+  }
+  double x[RPL];
+  load_rows<FMT, RPL, double>(g.seg(j, ch), (int64_t)lane * RPL, x);
+#pragma unroll
+  for (int r = 0; r < RPL; ++r)
+    xu[c * g.n_pad + row0 + r] = row0 + r < g.n ? (x[r] - cm[j]) * cinv[j] : 0.0;
+}
+
+template <int FMT, int RPL>
+static void dense_cols_fmt(const Geom& g, const int64_t* cols, int64_t nu, const double* cm,
+                           const double* cinv, double* xu, hipStream_t s) {
+  hipLaunchKernelGGL((k_dense_cols<FMT, RPL>), dim3((unsigned)g.nchunks(), (unsigned)nu), dim3(64),
+                     0, s, g, cols, cm, cinv, xu);
+}
+
+// out[a * nb + b] = xa^T xb for rows of A (na x m) and B (nb x m), one block per pair.
+__global__ __launch_bounds__(256) void k_cross(const double* A, const double* B, int64_t m,
+                                               int64_t nb, double* out) {
+  __shared__ double red[4];
+  const int64_t a = blockIdx.y, b = blockIdx.x;
+  double q[1] = {0.0};
+  for (int64_t i = threadIdx.x; i < m; i += 256) q[0] += A[a * m + i] * B[b * m + i];
+  block_sum<256, 1, double>(q, red);
+  if (threadIdx.x == 0) out[a * nb + b] = q[0];
+}
+
+// theta1 = theta' - X~_U c in place; per block the largest box scale factor.
+__global__ __launch_bounds__(256) void k_unpen_apply(double* tp, const double* xu,
+                                                    const double* c, int64_t nu, int64_t n,
+                                                    int64_t n_pad, double lo, double hi,
+                                                    double* bmin) {
+  __shared__ double red[4];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double sc = 1.0;
+  if (i < n) {
+    double t = tp[i];
+    for (int64_t a = 0; a < nu; ++a) t -= xu[a * n_pad + i] * c[a];
+    tp[i] = t;
+    if (t > hi) sc = hi / t;
+    else if (t < lo) sc = lo / t;
+  }
+  sc = -wave_max(-sc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sc;
+  __syncthreads();
+  if (threadIdx.x == 0) bmin[blockIdx.x] = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+}
+
+// theta2 = s theta1 with s the smallest block factor; out[2] = y^T theta2,
+// out[5] = sum theta2 (single block, deterministic order).
+__global__ __launch_bounds__(1024) void k_unpen_scale(double* tp, const double* y, int64_t n,
+                                                      const double* bmin, int64_t nblk, double* out) {
+  __shared__ double red[2 * 16];
+  __shared__ double s_sh;
+  if (threadIdx.x == 0) {
+    double s = 1.0;
+    for (int64_t b = 0; b < nblk; ++b) s = fmin(s, bmin[b]);
+    s_sh = s;
+  }
+  __syncthreads();
+  const double s = s_sh;
+  double q[2] = {0.0, 0.0};
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    const double t = tp[i] * s;
+    tp[i] = t;
+    q[0] += t * y[i];
+    q[1] += t;
+  }
+  block_sum<1024, 2, double>(q, red);
+  if (threadIdx.x == 0) { out[2] = q[0]; out[5] = q[1]; out[6] = s; }
+}
+
+hipError_t launch_dense_cols(const Geom& g, const int64_t* cols, int64_t nu, const double* cm,
+                             const double* cinv, double* xu, hipStream_t s) {
+  if (nu < 1) return hipSuccess;
+  PQR_DISPATCH64(dense_cols_fmt, g, cols, nu, cm, cinv, xu, s)
+  return hipGetLastError();
+}
+
+hipError_t launch_cross(const double* A, int64_t na, const double* B, int64_t nb, int64_t m,
+                        double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_cross, dim3((unsigned)nb, (unsigned)na), dim3(256), 0, s, A, B, m, nb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpen_project(double* tp, const double* xu, const double* c, int64_t nu,
+                                int64_t n, int64_t n_pad, double tau, const double* y,
+                                double* bpart, double* out, hipStream_t s) {
+  const unsigned nb = (unsigned)(n_pad / 256);
+  hipLaunchKernelGGL(k_unpen_apply, dim3(nb), dim3(256), 0, s, tp, xu, c, nu, n, n_pad,
+                     (tau - 1.0) / (double)n, tau / (double)n, bpart);
+  hipLaunchKernelGGL(k_unpen_scale, dim3(1), dim3(1024), 0, s, tp, y, n, bpart, (int64_t)nb, out);
+  return hipGetLastError();
+}
+
+// LLA weights (Algorithm 2): w_j = max(p'_lambda(|beta_j|) / lambda, wfloor) with
+// p' the SCAD derivative of eq. scad (kind 0) or the MCP derivative of eq. mcp
+// (kind 1), beta on the standardized scale; out[0] = 0 (intercept), out[1 + j].
+template <typename T>
+__global__ __launch_bounds__(256) void k_lla_weights(const T* __restrict__ beta, int64_t p,
+                                                     int kind, double a, double lam,
+                                                     double wfloor, double* out) {
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j <= p; j += (int64_t)gridDim.x * 256) {
+    if (j == 0) { out[0] = 0.0; continue; }
+    const double b = fabs((double)beta[j - 1]);
+    double d;
+    if (kind == 0)
+      d = b <= lam ? lam : (b < a * lam ? (a * lam - b) / (a - 1.0) : 0.0);   // eq. scad
+    else
+      d = b <= a * lam ? lam - b / a : 0.0;                                   // eq. mcp
+    out[j] = fmax(d / lam, wfloor);
+  }
+}
+
+template <typename T>
+hipError_t launch_lla_weights(const T* beta, int64_t p, int kind, double a, double lam,
+                              double wfloor, double* out, hipStream_t s) {
+  hipLaunchKernelGGL((k_lla_weights<T>), dim3(1024), dim3(256), 0, s, beta, p, kind, a, lam, wfloor,
+                     out);
+  return hipGetLastError();
+}
+template hipError_t launch_lla_weights<float>(const float*, int64_t, int, double, double, double, double*, hipStream_t);
+template hipError_t launch_lla_weights<double>(const double*, int64_t, int, double, double, double, double*, hipStream_t);
 
 hipError_t launch_scale(const double* w, double a, int64_t m, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_scale, dim3(1024), dim3(256), 0, s, w, a, m, out);

@@ -68,6 +68,14 @@ struct pqr_ctx {
   double* out4 = nullptr;           // 4 x 8 certificate outputs
   double* gmax4 = nullptr;          // 4 x ngroups dual-ratio partials
   int max_code = -1;                // largest byte of an int8 store (-1: not measured)
+  // unpenalized feature columns (weight 0) of the current problem, for the certificate
+  std::vector<int64_t> unpen;
+  bool unpen_ready = false;
+  int64_t* unpen_cols_d = nullptr;
+  double *unpen_x = nullptr, *unpen_c = nullptr, *unpen_u = nullptr;
+  int64_t unpen_cap = 0;
+  std::vector<double> unpen_chol;   // Cholesky factor of X~_U^T X~_U (+ tiny ridge), row-major
+  std::vector<double> unpen_diag;   // ||x~_j||^2
 };
 
 namespace {
@@ -474,6 +482,21 @@ struct SolveSetup {
   IterParams ip;
 };
 
+// The unpenalized feature columns (weight 0) of the problem; the certificate
+// projects its dual point onto x~_j^T theta = 0 for them.
+void set_unpenalized(pqr_ctx* ctx, const double* weights) {
+  std::vector<int64_t> u;
+  if (weights)
+    for (int64_t j = 0; j < ctx->g.p; ++j)
+      if (weights[1 + j] == 0.0) u.push_back(j);
+  if (u != ctx->unpen) {
+    ctx->unpen.swap(u);
+    ctx->unpen_ready = false;
+  }
+}
+
+pqr_status project_unpenalized(pqr_ctx* ctx, double tau, bool* ok);
+
 template <typename T>
 pqr_status upload_problem(pqr_ctx* ctx, const double* y, double tau, double lambda,
                           const double* weights, double* lmax_out, double* score) {
@@ -498,6 +521,7 @@ pqr_status upload_problem(pqr_ctx* ctx, const double* y, double tau, double lamb
   if (lmax_out) *lmax_out = ctx->out_h[3];
   for (int64_t j = 0; j < g.p; ++j) lh[j] *= lambda;
   HIPCHK(hipMemcpyAsync(ctx->clam_d, lh.data(), g.p_pad * 8, hipMemcpyHostToDevice, s));
+  set_unpenalized(ctx, weights);
   HIPCHK(launch_from_double<T>(ctx->clam_d, g.p_pad, (T*)ctx->clam_t, s));
   HIPCHK(hipStreamSynchronize(s));
   return PQR_OK;
@@ -597,6 +621,87 @@ struct Cert {
   double primal, dual, gap, rel_gap, maxratio;
 };
 
+// Dual feasibility for the unpenalized columns U (lambda_j = 0): project the
+// projected theta' (ctx->theta_p) onto {sum theta = 0, x~_U^T theta = 0} and scale
+// it back into the box (launch_unpen_project).  The Gram matrix of X~_U and its Cholesky factor
+// (with a ridge of 1e-12 of its largest diagonal, so that constant columns get
+// c_j = 0) are built once per problem.  *ok is false when a residual x~_j^T theta
+// is above rounding level (1e-10 ||x~_j|| ||theta||): the certificate then gives
+// no dual bound.
+pqr_status project_unpenalized(pqr_ctx* ctx, double tau, bool* ok) {
+  const Geom& g = ctx->g;
+  hipStream_t s = ctx->s;
+  const int64_t nu = (int64_t)ctx->unpen.size() + 1;   // + the intercept (ones)
+  if (nu > 4097) {
+    ctx->err = "at most 4096 unpenalized columns (zero weights) are supported";
+    return PQR_ERR_UNSUPPORTED;
+  }
+  if (!ctx->unpen_ready) {
+    if (ctx->unpen_cap < nu) {
+      TRY(dalloc(ctx, &ctx->unpen_cols_d, (size_t)nu * 8));
+      TRY(dalloc(ctx, &ctx->unpen_x, (size_t)nu * g.n_pad * 8));
+      TRY(dalloc(ctx, &ctx->unpen_c, (size_t)nu * 8));
+      TRY(dalloc(ctx, &ctx->unpen_u, (size_t)nu * nu * 8));
+      ctx->unpen_cap = nu;
+    }
+    std::vector<int64_t> cols(1, -1);
+    cols.insert(cols.end(), ctx->unpen.begin(), ctx->unpen.end());
+    HIPCHK(hipMemcpyAsync(ctx->unpen_cols_d, cols.data(), nu * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(launch_dense_cols(g, ctx->unpen_cols_d, nu, ctx->cm_d, ctx->cinv_d, ctx->unpen_x, s));
+    HIPCHK(launch_cross(ctx->unpen_x, nu, ctx->unpen_x, nu, g.n_pad, ctx->unpen_u, s));
+    std::vector<double> G((size_t)nu * nu);
+    HIPCHK(hipMemcpyAsync(G.data(), ctx->unpen_u, G.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    ctx->unpen_diag.resize(nu);
+    double dmax = 0.0;
+    for (int64_t a = 0; a < nu; ++a) {
+      ctx->unpen_diag[a] = G[a * nu + a];
+      dmax = std::max(dmax, G[a * nu + a]);
+    }
+    const double ridge = 1e-12 * std::max(dmax, 1e-300);
+    for (int64_t a = 0; a < nu; ++a) G[a * nu + a] += ridge;
+    for (int64_t a = 0; a < nu; ++a) {   // in-place Cholesky, lower triangle
+      for (int64_t b = 0; b <= a; ++b) {
+        double v = G[a * nu + b];
+        for (int64_t k = 0; k < b; ++k) v -= G[a * nu + k] * G[b * nu + k];
+        G[a * nu + b] = a == b ? std::sqrt(std::max(v, ridge)) : v / G[b * nu + b];
+      }
+    }
+    ctx->unpen_chol.swap(G);
+    ctx->unpen_ready = true;
+  }
+  // u = X~_U^T theta', c = (L L^T)^{-1} u
+  HIPCHK(launch_cross(ctx->unpen_x, nu, ctx->theta_p, 1, g.n_pad, ctx->unpen_u, s));
+  std::vector<double> c(nu);
+  HIPCHK(hipMemcpyAsync(c.data(), ctx->unpen_u, nu * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const std::vector<double>& Lf = ctx->unpen_chol;
+  for (int64_t a = 0; a < nu; ++a) {
+    double v = c[a];
+    for (int64_t k = 0; k < a; ++k) v -= Lf[a * nu + k] * c[k];
+    c[a] = v / Lf[a * nu + a];
+  }
+  for (int64_t a = nu - 1; a >= 0; --a) {
+    double v = c[a];
+    for (int64_t k = a + 1; k < nu; ++k) v -= Lf[k * nu + a] * c[k];
+    c[a] = v / Lf[a * nu + a];
+  }
+  HIPCHK(hipMemcpyAsync(ctx->unpen_c, c.data(), nu * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(launch_unpen_project(ctx->theta_p, ctx->unpen_x, ctx->unpen_c, nu, g.n, g.n_pad, tau,
+                              ctx->y_d, ctx->bpart64, ctx->out_d, s));
+  // residual check
+  HIPCHK(launch_cross(ctx->unpen_x, nu, ctx->theta_p, 1, g.n_pad, ctx->unpen_u, s));
+  std::vector<double> r(nu);
+  HIPCHK(hipMemcpyAsync(r.data(), ctx->unpen_u, nu * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const double tnorm = std::sqrt((double)g.n) * std::max(tau, 1.0 - tau) / (double)g.n;
+  *ok = true;
+  for (int64_t a = 0; a < nu; ++a)
+    if (std::fabs(r[a]) > 1e-10 * std::sqrt(ctx->unpen_diag[a]) * tnorm) *ok = false;
+  return PQR_OK;
+}
+
 // FP64 certificate of the point (beta, beta0 = ctl->beta0, theta); `list` and
 // ctl->count must describe the nonzero groups of beta; ctx->clam_d holds lambda_j.
 template <typename T>
@@ -605,6 +710,8 @@ pqr_status certify_point(pqr_ctx* ctx, double tau, const T* theta, const T* beta
   const Geom& g = ctx->g;
   hipStream_t s = ctx->s;
   HIPCHK(launch_project<T>(theta, g.n, g.n_pad, tau, ctx->y_d, ctx->theta_p, ctx->out_d, s));
+  bool unpen_ok = true;
+  if (!ctx->unpen.empty()) TRY(project_unpenalized(ctx, tau, &unpen_ok));
   HIPCHK(launch_dots64(g, ctx->theta_p, ctx->out_d + 5, ctx->cm_d, ctx->cinv_d, ctx->clam_d,
                        nullptr, ctx->gpart, s));
   HIPCHK(launch_reduce_max(ctx->gpart, g.ngroups(), ctx->bpart64, ctx->out_d + 3, s));
@@ -626,7 +733,8 @@ pqr_status certify_point(pqr_ctx* ctx, double tau, const T* theta, const T* beta
   HIPCHK(hipStreamSynchronize(s));
   const double* o = ctx->out_h;
   const double mr = o[3];
-  const double alpha = mr > 1.0 ? (std::isinf(mr) ? 0.0 : 1.0 / mr) : 1.0;
+  double alpha = mr > 1.0 ? (std::isinf(mr) ? 0.0 : 1.0 / mr) : 1.0;
+  if (!unpen_ok) alpha = 0.0;   // the projection left x~_U^T theta above rounding level
   out->primal = o[0] + o[1];
   out->dual = alpha * o[2];
   out->gap = out->primal - out->dual;
@@ -1031,6 +1139,50 @@ pqr_status iterate_impl(pqr_ctx* ctx, const double* y, double tau, double lambda
 }
 }  // namespace
 
+// Algorithm 2: L-step LLA for SCAD / MCP on top of the weighted-l1 solve.
+extern "C" pqr_status pqr_solve_lla(pqr_ctx* ctx, const double* y, double tau, double lambda,
+                                    int penalty, double a, int L, double wfloor,
+                                    double* weights_out, int64_t* stage_iters, pqr_result* out) {
+  if (!ctx) return PQR_ERR_INVALID_ARG;
+  if (penalty != 0 && penalty != 1) {
+    ctx->err = "penalty must be 0 (SCAD) or 1 (MCP)";
+    return PQR_ERR_INVALID_ARG;
+  }
+  if (!(std::isfinite(a) && (penalty == 0 ? a > 2.0 : a > 1.0))) {
+    ctx->err = "SCAD needs a > 2, MCP needs a > 1";
+    return PQR_ERR_INVALID_ARG;
+  }
+  if (L < 0 || !(wfloor >= 0.0 && wfloor <= 1.0) || !(lambda > 0.0) || !std::isfinite(lambda)) {
+    ctx->err = "pqr_solve_lla needs L >= 0, 0 <= wfloor <= 1 and lambda > 0";
+    return PQR_ERR_INVALID_ARG;
+  }
+  const Geom& g = ctx->g;
+  std::vector<double> w(g.p + 1, 1.0);
+  w[0] = 0.0;
+  pqr_result tmp{};
+  pqr_result* res = out ? out : &tmp;
+  // stage 0: the weighted-l1 solve at unit weights from a zero start
+  pqr_status st = pqr_solve(ctx, y, tau, lambda, nullptr, PQR_START_ZERO, nullptr, res);
+  if (stage_iters) stage_iters[0] = res->iters;
+  if (st != PQR_OK) return st;
+  for (int l = 1; l <= L; ++l) {
+    // weights from the stage's returned (best primal) coefficients, on the device
+    if (ctx->opt.iter_prec == PQR_ITER_F64)
+      HIPCHK(launch_lla_weights<double>((const double*)ctx->beta_best, g.p, penalty, a, lambda,
+                                        wfloor, ctx->scratch64, ctx->s));
+    else
+      HIPCHK(launch_lla_weights<float>((const float*)ctx->beta_best, g.p, penalty, a, lambda,
+                                       wfloor, ctx->scratch64, ctx->s));
+    HIPCHK(hipMemcpyAsync(w.data(), ctx->scratch64, (g.p + 1) * 8, hipMemcpyDeviceToHost, ctx->s));
+    HIPCHK(hipStreamSynchronize(ctx->s));
+    st = pqr_solve(ctx, y, tau, lambda, w.data(), PQR_START_DEVICE, nullptr, res);
+    if (stage_iters) stage_iters[l] = res->iters;
+    if (st != PQR_OK) return st;
+  }
+  if (weights_out) std::memcpy(weights_out, w.data(), (g.p + 1) * 8);
+  return PQR_OK;
+}
+
 extern "C" pqr_status pqr_iterate(pqr_ctx* ctx, const double* y, double tau, double lambda,
                                   const double* weights, double mu, const double* eta,
                                   int64_t iters, double* beta_std, double* z, double* theta) {
@@ -1071,6 +1223,9 @@ static pqr_status kkt_impl(pqr_ctx* ctx, const double* y, double tau, double lam
   HIPCHK(hipMemcpyAsync(ctx->ctl_kkt, &c, sizeof(Ctl), hipMemcpyHostToDevice, s));
   HIPCHK(launch_project<double>(ctx->scratch64, g.n, g.n_pad, tau, ctx->y_d, ctx->theta_p,
                                 ctx->out_d, s));
+  set_unpenalized(ctx, weights);
+  bool unpen_ok = true;
+  if (!ctx->unpen.empty()) TRY(project_unpenalized(ctx, tau, &unpen_ok));
   HIPCHK(launch_dots64(g, ctx->theta_p, ctx->out_d + 5, ctx->cm_d, ctx->cinv_d, ctx->clam_d,
                        v_out ? ctx->v_d : nullptr, ctx->gpart, s));
   HIPCHK(launch_reduce_max(ctx->gpart, g.ngroups(), ctx->bpart64, ctx->out_d + 3, s));
@@ -1092,7 +1247,8 @@ static pqr_status kkt_impl(pqr_ctx* ctx, const double* y, double tau, double lam
   HIPCHK(hipStreamSynchronize(s));
   const double* o = ctx->out_h;
   const double mr = o[3];
-  const double alpha = mr > 1.0 ? (std::isinf(mr) ? 0.0 : 1.0 / mr) : 1.0;
+  double alpha = mr > 1.0 ? (std::isinf(mr) ? 0.0 : 1.0 / mr) : 1.0;
+  if (!unpen_ok) alpha = 0.0;   // the projection left x~_U^T theta above rounding level
   rep[0] = o[0] + o[1];
   rep[1] = alpha * o[2];
   rep[2] = (rep[0] - rep[1]) / std::max(std::fabs(rep[0]), 1e-300);
@@ -1204,6 +1360,12 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
     return PQR_ERR_INVALID_ARG;
   }
   for (int k = 0; k < K; ++k) TRY(validate_problem(ctx, y, taus[k], lambdas[k], weights));
+  if (weights)
+    for (int64_t j = 1; j <= g.p; ++j)
+      if (weights[j] == 0.0) {
+        ctx->err = "batched solves need positive weights (unpenalized columns: use pqr_solve)";
+        return PQR_ERR_UNSUPPORTED;
+      }
   if (ctx->max_code < 0) {   // the matrix cores read the int8 codes as signed
     int* mc = nullptr;
     TRY(dalloc(ctx, &mc, 64));

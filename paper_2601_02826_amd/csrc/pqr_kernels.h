@@ -229,6 +229,21 @@ hipError_t launch_max_code(const Geom& g, int* out, hipStream_t s);
 template <typename T>
 hipError_t launch_active_list(const Geom& g, const IterBufs<T>& b, hipStream_t s);
 hipError_t launch_scale(const double* w, double a, int64_t m, double* out, hipStream_t s);
+// Unpenalized columns in the certificate: dense standardized copies of cols[0..nu)
+// (nu x n_pad), cross products out = A B^T (na x nb, rows of length m), and the
+// projection of tp onto x~_U^T theta = 0 (c solves the normal equations) followed
+// by the box scaling; out[2] = y^T theta, out[5] = sum theta, out[6] = the scale.
+hipError_t launch_dense_cols(const Geom& g, const int64_t* cols, int64_t nu, const double* cm,
+                             const double* cinv, double* xu, hipStream_t s);
+hipError_t launch_cross(const double* A, int64_t na, const double* B, int64_t nb, int64_t m,
+                        double* out, hipStream_t s);
+hipError_t launch_unpen_project(double* tp, const double* xu, const double* c, int64_t nu,
+                                int64_t n, int64_t n_pad, double tau, const double* y,
+                                double* bpart, double* out, hipStream_t s);
+// LLA stage weights out[0..p] (out[0] = 0) from standardized coefficients beta[0..p)
+template <typename T>
+hipError_t launch_lla_weights(const T* beta, int64_t p, int kind, double a, double lam,
+                              double wfloor, double* out, hipStream_t s);
 }  // namespace pqr
 
 namespace pqr {

@@ -1,0 +1,88 @@
+"""Folded-concave penalties by LLA (Algorithm 2) on the GPU: the stage weights are
+the SCAD / MCP derivatives (eq. scad, eq. mcp) of the previous stage's coefficients,
+and every stage is the weighted-l1 problem solved to its certified gap, equal to the
+LP optimum of that weighted problem."""
+import numpy as np
+import pytest
+
+from oracle import lp, pqr
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("penalty,a,L", [("scad", 3.7, 1), ("mcp", 3.0, 2)])
+def test_lla_stages(penalty, a, L):
+    import paper_2601_02826_amd as pq
+    n, p, tau, tol = 400, 150, 0.5, 1e-6
+    X, y = H.genotype_problem(n, p, seed=71, n_causal=6)
+    X1, _, _ = H.oracle_design(X, True)
+    ctx = pq.Context.from_tensor(H.to_device_cols(X.astype(np.uint8), np.uint8), store_fmt="i8",
+                                 G=3, tol_gap=tol, cert_every=100, max_iter=2_000_000,
+                                 iter_prec="f64")
+    lam = 0.25 * ctx.lambda_max(y, tau)
+    lasso = ctx.solve_lla(y, tau, lam, penalty=penalty, a=a, L=0)
+    print(f"stage 0: {lasso['stage_iters']} iterations", flush=True)
+    prev = lasso if L == 1 else ctx.solve_lla(y, tau, lam, penalty=penalty, a=a, L=L - 1)
+    print(f"stages 0..{L - 1}: {prev['stage_iters']} iterations", flush=True)
+    res = ctx.solve_lla(y, tau, lam, penalty=penalty, a=a, L=L)
+    print(f"stages 0..{L}: {res['stage_iters']} iterations, gap {res['rel_gap']:.2e}", flush=True)
+    # the weights: the penalty derivative of the previous stage's coefficients / lambda
+    # (same arithmetic in numpy); zero weights (unpenalized columns) are certified by
+    # the projected dual point
+    d = pqr.scad_deriv if penalty == "scad" else pqr.mcp_deriv
+    want = d(prev["beta_std"][1:], lam, a=a) / lam
+    assert res["weights"][0] == 0.0
+    assert np.allclose(res["weights"][1:], want, rtol=1e-13, atol=0)
+    assert np.any(res["weights"][1:] == 0.0)           # large coefficients are unpenalized
+    # the last stage: certified and equal to the LP optimum of its weighted problem
+    lam_vec = lam * res["weights"]
+    lam_vec[0] = 0.0
+    val, _ = lp.highs(X1, y, tau, lam_vec)
+    obj = pqr.objective(X1, y, res["beta_std"], tau, lam_vec)
+    assert res["rel_gap"] <= tol
+    assert val * (1 - 1e-12) <= obj <= val * (1 + tol) + 1e-12
+    assert len(res["stage_iters"]) == L + 1 and all(k > 0 for k in res["stage_iters"])
+    # the stage minimises its weighted objective: no worse there than the lasso stage
+    assert obj <= pqr.objective(X1, y, lasso["beta_std"], tau, lam_vec) * (1 + tol)
+    ctx.close()
+
+
+def test_lla_error_paths():
+    import paper_2601_02826_amd as pq
+    X, y = H.genotype_problem(300, 100, seed=72)
+    ctx = pq.Context.from_tensor(H.to_device_cols(X.astype(np.uint8), np.uint8), store_fmt="i8", G=2)
+    for kw in [dict(penalty="scad", a=2.0), dict(penalty="mcp", a=1.0), dict(L=-1),
+               dict(wfloor=-0.1)]:
+        with pytest.raises(pq.PQRError) as e:
+            ctx.solve_lla(y, 0.5, 0.05, **kw)
+        assert e.value.status == pq.PQR_ERR_INVALID_ARG
+    ctx.close()
+
+
+def test_certificate_with_unpenalized_columns_matches_oracle():
+    """pqr_kkt with zero weights against the oracle's certificate at the same point:
+    the same projected dual point, hence the same primal and dual values."""
+    import paper_2601_02826_amd as pq
+    n, p, tau = 500, 120, 0.35
+    X, y = H.genotype_problem(n, p, seed=73, n_causal=5)
+    X1, _, _ = H.oracle_design(X, True)
+    ctx = pq.Context.from_tensor(H.to_device_cols(X.astype(np.uint8), np.uint8), store_fmt="i8",
+                                 G=2, iter_prec="f64")
+    lam = 0.2 * ctx.lambda_max(y, tau)
+    w = np.ones(p + 1)
+    w[[3, 17, 64]] = 0.0
+    rng = np.random.default_rng(5)
+    beta = np.zeros(p + 1)
+    beta[rng.choice(p, 8, replace=False) + 1] = rng.standard_normal(8) * 0.1
+    theta = (rng.random(n) - 0.5) * 1.5 / n
+    lam_vec = lam * w
+    lam_vec[0] = 0.0
+    got = ctx.kkt(y, tau, lam, beta, theta, weights=w)
+    want = pqr.dual_certificate(X1, y, tau, lam_vec, beta, theta)
+    assert got["primal"] == pytest.approx(want["primal"], rel=1e-12)
+    assert got["dual"] == pytest.approx(want["dual"], rel=1e-9, abs=1e-14)
+    assert want["alpha"] > 0 and got["dual"] != 0.0
+    val, _ = lp.highs(X1, y, tau, lam_vec)
+    assert got["dual"] <= val + 1e-12
+    ctx.close()

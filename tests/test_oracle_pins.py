@@ -224,6 +224,41 @@ def test_certificate_weak_duality():
         assert c["gap"] >= c["primal"] - val - 1e-12
 
 
+@pytest.mark.parametrize("standardized", [True, False])
+def test_certificate_weak_duality_with_unpenalized_columns(standardized):
+    """lam_j = 0 on some feature columns: the certificate's dual point satisfies
+    sum theta = 0 and x_j^T theta = 0 there (to rounding) and still bounds the LP
+    optimum from below; on a raw design the columns are not orthogonal to the
+    intercept, so the projection has to keep sum theta = 0 itself."""
+    rng = np.random.default_rng(11)
+    n, p = 40, 10
+    X = rng.integers(0, 3, (n, p)).astype(float) + (0 if standardized else 0.5)
+    Xs = pqr.standardize(X)[0] if standardized else X
+    X1 = pqr.with_intercept(Xs)
+    y = X1[:, 1:4] @ np.array([1.0, -0.5, 0.8]) + rng.standard_t(3, n)
+    tau = 0.6
+    lam = np.full(p + 1, 0.1 * pqr.lambda_max(X1, y, tau))
+    lam[0] = 0
+    lam[[2, 5]] = 0.0                                   # two unpenalized features
+    val, beta_lp = lp.highs(X1, y, tau, lam)
+    for _ in range(30):
+        beta = rng.standard_normal(p + 1) * 0.3
+        theta = rng.standard_normal(n) * 0.02
+        c = pqr.dual_certificate(X1, y, tau, lam, beta, theta)
+        t = c["theta_feasible"]
+        assert abs(t.sum()) < 1e-15 and np.max(np.abs(X1[:, [2, 5]].T @ t)) < 1e-15
+        assert np.all(t >= (tau - 1) / n - 1e-18) and np.all(t <= tau / n + 1e-18)
+        assert c["dual"] <= val + 1e-12
+        assert c["alpha"] > 0
+    # a converged FS-QRPPA run certifies, to a small gap, the LP optimum
+    blocks = pqr.partition(p, 2)
+    mu = pqr.default_mu(y, 2)
+    eta = pqr.step_sizes(X1, blocks, mu)
+    res = pqr.fsqrppa(X1, y, tau, lam, blocks, mu, eta, tol_gap=1e-8, max_iter=400_000)
+    assert res["rel_gap"] <= 1e-8
+    assert val * (1 - 1e-12) <= res["primal"] <= val * (1 + 1e-8) + 1e-12
+
+
 def test_h_norm_successive_difference_non_increasing():
     X1, y = _tiny(4, 70, 40)
     tau, G = 0.5, 4
