@@ -204,7 +204,8 @@ pqr_status pqr_iterate(pqr_ctx* ctx, const double* y, double tau, double lambda,
  * over the floored columns.
  *  weights_out  NULL or host, p+1 doubles: the last stage's weights (w_0 = 0)
  *  stage_iters  NULL or host, L+1 iteration counts
- *  out          the last stage's result (as pqr_solve)
+ *  out          the last stage's result (as pqr_solve); with opt.profile, sweep_ms
+ *               and sweep_launches are summed over all stages
  * Stops at the first stage that does not return PQR_OK and returns its status. */
 pqr_status pqr_solve_lla(pqr_ctx* ctx, const double* y, double tau, double lambda,
                          int penalty, double a, int L, double wfloor, double* weights_out,

@@ -357,7 +357,9 @@ class Context:
         self._check(st, ok)
         return Result(beta=beta, beta_std=beta_std, z=z, theta=theta, iters=out.iters,
                       nnz=out.nnz, primal=out.primal, dual=out.dual, rel_gap=out.rel_gap,
-                      seconds=out.seconds, status=st, weights=w, stage_iters=list(its))
+                      seconds=out.seconds, sweep_ms=out.sweep_ms,
+                      sweep_launches=out.sweep_launches, status=st, weights=w,
+                      stage_iters=list(its))
 
     def kkt(self, y, tau, lam, beta_std, theta, weights=None):
         rep = np.zeros(4)

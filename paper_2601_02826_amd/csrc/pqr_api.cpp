@@ -1164,6 +1164,8 @@ extern "C" pqr_status pqr_solve_lla(pqr_ctx* ctx, const double* y, double tau, d
   // stage 0: the weighted-l1 solve at unit weights from a zero start
   pqr_status st = pqr_solve(ctx, y, tau, lambda, nullptr, PQR_START_ZERO, nullptr, res);
   if (stage_iters) stage_iters[0] = res->iters;
+  double sweep_ms = res->sweep_ms;
+  int64_t sweeps = res->sweep_launches;
   if (st != PQR_OK) return st;
   for (int l = 1; l <= L; ++l) {
     // weights from the stage's returned (best primal) coefficients, on the device
@@ -1177,6 +1179,10 @@ extern "C" pqr_status pqr_solve_lla(pqr_ctx* ctx, const double* y, double tau, d
     HIPCHK(hipStreamSynchronize(ctx->s));
     st = pqr_solve(ctx, y, tau, lambda, w.data(), PQR_START_DEVICE, nullptr, res);
     if (stage_iters) stage_iters[l] = res->iters;
+    sweep_ms += res->sweep_ms;
+    sweeps += res->sweep_launches;
+    res->sweep_ms = sweep_ms;          // with opt.profile: summed over the stages
+    res->sweep_launches = sweeps;
     if (st != PQR_OK) return st;
   }
   if (weights_out) std::memcpy(weights_out, w.data(), (g.p + 1) * 8);
