@@ -1501,6 +1501,39 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
       if (!done[k]) ks.push_back(k);
     return ks;
   };
+  // Certificate schedule (each certificate is a full FP64 pass over X per four
+  // right-hand sides): from the last two certified gaps of a right-hand side the
+  // rounds still needed to reach the target are extrapolated (log-linear) and its
+  // next certificate is due after 80 % of them, at least 1 and at most 8 rounds.
+  std::vector<int64_t> last_round(K, -1000), next_round(K, 0), gap_wait(K, 1);
+  auto wait_of = [&](int k) { return gap_wait[k]; };
+  std::vector<double> prev_rel(K, INFINITY);
+  int64_t round = 0;
+  auto due = [&]() {
+    std::vector<int> ks;
+    for (int k = 0; k < K; ++k)
+      if (!done[k] && round >= next_round[k]) {
+        ks.push_back(k);
+        last_round[k] = round;
+      }
+    ++round;
+    return ks;
+  };
+  auto reschedule = [&](const std::vector<int>& ks) {
+    const double tol = ctx->opt.tol_gap;
+    for (int k : ks) {
+      int64_t wait = 1;
+      if (std::isfinite(prev_rel[k]) && std::isfinite(rel[k]) && rel[k] > tol && rel[k] < prev_rel[k] &&
+          tol > 0) {
+        const double rate = std::log(prev_rel[k] / rel[k]) / (double)std::max<int64_t>(1, wait_of(k));
+        const double need = std::log(rel[k] / tol) / rate;
+        wait = std::max<int64_t>(1, std::min<int64_t>(8, (int64_t)(0.8 * need)));
+      }
+      prev_rel[k] = rel[k];
+      next_round[k] = last_round[k] + wait;
+      gap_wait[k] = wait;
+    }
+  };
   const bool prof = ctx->opt.profile != 0;
   if (prof && ctx->events.size() < 2 * (size_t)ctx->opt.cert_every) {
     const size_t old = ctx->events.size();
@@ -1526,11 +1559,21 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
       }
       gemm_launches += chunk;
     }
-    TRY(certify_many(pending()));
+    {
+      const std::vector<int> ks = due();
+      TRY(certify_many(ks));
+      reschedule(ks);
+    }
   }
   // the returned iterate of a frozen right-hand side is its certified point; the
-  // others were certified where max_iter left them (max_iter = 0: certify now)
-  if (it == 0) TRY(certify_many(pending()));
+  // others get a certificate of where max_iter left them unless the last round
+  // already took it
+  {
+    std::vector<int> ks;
+    for (int k = 0; k < K; ++k)
+      if (!done[k] && (it == 0 || last_round[k] != round - 1)) ks.push_back(k);
+    if (!ks.empty()) TRY(certify_many(ks));
+  }
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (outs) {
     std::vector<float> bf(g.p), vf(g.n);
