@@ -125,3 +125,30 @@ def test_solved_point_objective_and_dual_feasibility(full):
     ratios = np.abs(_std_cols(spec, cols).T @ tp) / lam
     assert np.all(ratios <= 1.0 + 5e-2)
     assert np.max(ratios[np.isin(cols, support)]) > 0.9
+
+
+def test_batched_path_objectives_and_dual_feasibility(full):
+    """The benchmark's default launch configuration at full size (20 right-hand sides
+    of one batched solve, padded to 32), on the sparse half of a path (lambda_max down
+    to 0.2 lambda_max, where every point stays sparse): every point is certified, its
+    reported objective is recomputed by the oracle from the support columns, and the
+    projected dual point is feasible on sampled columns."""
+    spec, g, ctx, sample = full
+    y = g["y"]
+    lmax = ctx.lambda_max(y, 0.5)
+    lams = lmax * 0.2 ** (np.arange(20) / 19.0)
+    res = ctx.solve_batch(y, np.full(20, 0.5), lams)
+    print(f"batched: {res[0]['iters']} iterations, nnz {[r['nnz'] for r in res]}", flush=True)
+    assert all(r["rel_gap"] <= 1e-3 for r in res)
+    for k in range(20):
+        r = res[k]
+        support = np.nonzero(r["beta_std"][1:])[0]
+        assert len(support) < 2000
+        Xs = _std_cols(spec, support) if len(support) else np.zeros((N, 0))
+        fit = r["beta_std"][0] + Xs @ r["beta_std"][1 + support]
+        primal = (np.mean(pqr.pinball(y - fit, 0.5)) +
+                  lams[k] * np.abs(r["beta_std"][1 + support]).sum())
+        assert r["primal"] == pytest.approx(primal, rel=1e-9)
+        tp = pqr.project_box_sum(r["theta"], -0.5 / N, 0.5 / N)
+        ratios = np.abs(_std_cols(spec, sample).T @ tp) / lams[k]
+        assert np.all(ratios <= 1.0 + 5e-2)
