@@ -81,10 +81,16 @@ __global__ void k_bdsum(BatchBufs b, int nblk, int Kp) {
 // Epilogue: the weighted soft threshold of eq. beta_update for every (column,
 // k) and per (group, tile) a 16-bit mask of the columns nonzero for some k.
 // ---------------------------------------------------------------------------
-constexpr int kDRow = 128 + 16;   // LDS bytes per digit row of a 128-row tile (+16: banks)
+// LDS bytes per digit row of a tile of 64 SPT rows (+16: bank spread)
+template <int SPT> constexpr int drow_bytes() { return 64 * SPT + 16; }
 
-template <int TW, int GW, int DL>
-__global__ __launch_bounds__(256, 2) void k_bgemm(Geom g, BatchBufs b, int Kp, int wps) {
+// SPT = 64-row steps per digit tile: 2 (one barrier per 128 rows) or, where two
+// tiles of every right-hand side would not leave LDS for two blocks per CU, 1.
+// WPB = wavefronts per block: 4, or 8 when several wavefronts share a group set
+// (more groups per block share each staged digit tile).
+template <int TW, int GW, int DL, int SPT, int WPB>
+__global__ __launch_bounds__(64 * WPB, 2) void k_bgemm(Geom g, BatchBufs b, int Kp, int wps) {
+  constexpr int kDRow = drow_bytes<SPT>();
   extern __shared__ __attribute__((aligned(16))) uint8_t dtile[];   // 2 x S*Kp x kDRow
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
@@ -93,7 +99,7 @@ __global__ __launch_bounds__(256, 2) void k_bgemm(Geom g, BatchBufs b, int Kp, i
   // wps wavefronts share one set of GW groups; wavefront wv % wps takes tiles r0..
   // A wavefront past the last group or tile still runs the loop (it takes part in
   // the digit tiles and the barriers) on clamped indices and skips the epilogue.
-  const int64_t gw0r = ((int64_t)blockIdx.x * (4 / wps) + wv / wps) * GW;
+  const int64_t gw0r = ((int64_t)blockIdx.x * (WPB / wps) + wv / wps) * GW;
   const int r0r = (wv % wps) * TW;
   const bool wave_live = gw0r < ng && r0r < nrt;
   const int64_t gw0 = gw0r < ng ? gw0r : ng - 1;
@@ -132,29 +138,30 @@ __global__ __launch_bounds__(256, 2) void k_bgemm(Geom g, BatchBufs b, int Kp, i
       af[q] = v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
     }
   };
-  // B: the digits of every right-hand side for 128 rows are staged once per block
-  // in LDS (row s*Kp + k: 128 bytes), double-buffered; a wavefront reads its
-  // fragments there (rhs (r0 + r)*16 + col, bytes 64 h + 16 kq of step half h).
-  const int drows = kBS * Kp, total16 = drows * 8;
+  // B: the digits of every right-hand side for 64 SPT rows are staged once per
+  // block in LDS (row s*Kp + k: 64 SPT bytes), double-buffered; a wavefront reads
+  // its fragments there (rhs (r0 + r)*16 + col, bytes 64 h + 16 kq of step h).
+  constexpr int kParts = 4 * SPT;                  // 16-byte pieces per digit row
+  const int drows = kBS * Kp, total16 = drows * kParts;
   const int64_t dbytes = (int64_t)drows * g.n_pad;
   const __amdgpu_buffer_rsrc_t brsrc = __builtin_amdgcn_make_buffer_rsrc(
       (void*)b.dig, (short)0, (int)(dbytes < 0x7fffffffll ? dbytes : 0x7fffffffll), 0x00020000);
   auto load_d = [&](int64_t u, v4u (&dr)[DL]) {
 #pragma unroll
     for (int i = 0; i < DL; ++i) {
-      const int idx = threadIdx.x + 256 * i;
-      const int row = idx < total16 ? idx >> 3 : 0, part = idx & 7;
+      const int idx = threadIdx.x + 64 * WPB * i;
+      const int row = idx < total16 ? idx / kParts : 0, part = idx % kParts;
       dr[i] = __builtin_amdgcn_raw_buffer_load_b128(brsrc, (int)((int64_t)row * g.n_pad + part * 16),
-                                                    (int)(u * 128), 0);
+                                                    (int)(u * 64 * SPT), 0);
     }
   };
   auto store_d = [&](int buf, const v4u (&dr)[DL]) {
 #pragma unroll
     for (int i = 0; i < DL; ++i) {
-      const int idx = threadIdx.x + 256 * i;
+      const int idx = threadIdx.x + 64 * WPB * i;
       if (idx < total16)
-        *reinterpret_cast<v4u*>(dtile + ((int64_t)buf * drows + (idx >> 3)) * kDRow + (idx & 7) * 16) =
-            dr[i];
+        *reinterpret_cast<v4u*>(dtile + ((int64_t)buf * drows + idx / kParts) * kDRow +
+                                (idx % kParts) * 16) = dr[i];
     }
   };
   auto read_b = [&](int buf, int h, v4i (&bf)[TW][kBS]) {
@@ -191,23 +198,48 @@ __global__ __launch_bounds__(256, 2) void k_bgemm(Geom g, BatchBufs b, int Kp, i
   __builtin_amdgcn_sched_barrier(0);   // set 0 strictly older than set 1 on entry
   load_a(1, aS[1]);
   __builtin_amdgcn_sched_barrier(0);
-  for (int64_t u = 0; u < nsup; ++u) {
-    const int buf = (int)(u & 1);
-    load_d(u + 1 < nsup ? u + 1 : u, dr);
-    __builtin_amdgcn_sched_barrier(0);
-    read_b(buf, 0, bf);
-    mma(aS[0], bf);
-    __builtin_amdgcn_sched_barrier(0);
-    const int64_t t2 = 2 * u + 2 < nsteps ? 2 * u + 2 : nsteps - 2;
-    load_a(t2, aS[0]);
-    __builtin_amdgcn_sched_barrier(0);
-    read_b(buf, 1, bf);
-    mma(aS[1], bf);
-    __builtin_amdgcn_sched_barrier(0);
-    load_a(t2 + 1, aS[1]);
-    __builtin_amdgcn_sched_barrier(0);
-    store_d(buf ^ 1, dr);
-    __syncthreads();
+  if constexpr (SPT == 2) {
+    for (int64_t u = 0; u < nsup; ++u) {
+      const int buf = (int)(u & 1);
+      load_d(u + 1 < nsup ? u + 1 : u, dr);
+      __builtin_amdgcn_sched_barrier(0);
+      read_b(buf, 0, bf);
+      mma(aS[0], bf);
+      __builtin_amdgcn_sched_barrier(0);
+      const int64_t t2 = 2 * u + 2 < nsteps ? 2 * u + 2 : nsteps - 2;
+      load_a(t2, aS[0]);
+      __builtin_amdgcn_sched_barrier(0);
+      read_b(buf, 1, bf);
+      mma(aS[1], bf);
+      __builtin_amdgcn_sched_barrier(0);
+      load_a(t2 + 1, aS[1]);
+      __builtin_amdgcn_sched_barrier(0);
+      store_d(buf ^ 1, dr);
+      __syncthreads();
+    }
+  } else {
+    // one 64-row tile per step: step t reads LDS buffer t & 1 (t even: 0)
+    for (int64_t t = 0; t < nsteps; t += 2) {
+      load_d(t + 1, dr);
+      __builtin_amdgcn_sched_barrier(0);
+      read_b(0, 0, bf);
+      mma(aS[0], bf);
+      __builtin_amdgcn_sched_barrier(0);
+      const int64_t t2 = t + 2 < nsteps ? t + 2 : nsteps - 2;
+      load_a(t2, aS[0]);
+      __builtin_amdgcn_sched_barrier(0);
+      store_d(1, dr);
+      __syncthreads();
+      load_d(t + 2 < nsteps ? t + 2 : t + 1, dr);
+      __builtin_amdgcn_sched_barrier(0);
+      read_b(1, 0, bf);
+      mma(aS[1], bf);
+      __builtin_amdgcn_sched_barrier(0);
+      load_a(t2 + 1, aS[1]);
+      __builtin_amdgcn_sched_barrier(0);
+      store_d(0, dr);
+      __syncthreads();
+    }
   }
   if (!wave_live) return;
   // epilogue: lane holds columns 4*kq + e (e = 0..3) of each group for rhs (r0+r)*16 + col
@@ -600,30 +632,29 @@ hipError_t launch_batch_iteration(const Geom& g, const BatchBufs& b, int Kp, dou
   // one or two tiles per wavefront, GW = 4 groups (GW * TW * S * 4 <= 96 accumulators);
   // wps = wavefronts sharing a set of groups (1, 2 or 4); LDS: two digit tiles
   {
-    const size_t lds = (size_t)2 * kBS * Kp * kDRow;
+    const bool small_tiles = nrt >= 6;   // 2 x 3 Kp x 144 bytes would leave one block per CU
+    const size_t lds = (size_t)2 * kBS * Kp * (small_tiles ? drow_bytes<1>() : drow_bytes<2>());
     const int wps = nrt <= 2 ? 1 : (nrt <= 4 ? 2 : 4);
-    const int64_t per_block = (int64_t)(4 / wps) * 4;   // groups per block (GW = 4)
+    const int wpb = wps >= 2 ? 8 : 4;
+    const int64_t per_block = (int64_t)(wpb / wps) * 4;   // groups per block (GW = 4)
     const dim3 grid((unsigned)((g.ngroups() + per_block - 1) / per_block));
     auto go = [&](auto kern) {
-      static bool attr_set = false;   // more than 64 KB of dynamic LDS needs the attribute
-      if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        attr_set = true;
-      }
+      // allow more than 64 KB of dynamic LDS for this kernel (a cheap host call)
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
       if (ev0) (void)hipEventRecord(ev0, s);
-      hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, g, b, Kp, wps);
+      hipLaunchKernelGGL(kern, grid, dim3(64 * wpb), lds, s, g, b, Kp, wps);
       if (ev1) (void)hipEventRecord(ev1, s);
     };
-    switch (nrt) {   // DL = ceil(24 Kp / 256) digit loads per thread and tile
-      case 1: go(k_bgemm<1, 4, 2>); break;
-      case 2: go(k_bgemm<2, 4, 3>); break;
-      case 3: go(k_bgemm<2, 4, 5>); break;
-      case 4: go(k_bgemm<2, 4, 6>); break;
-      case 5: go(k_bgemm<2, 4, 8>); break;
-      case 6: go(k_bgemm<2, 4, 9>); break;
-      case 7: go(k_bgemm<2, 4, 11>); break;
-      case 8: go(k_bgemm<2, 4, 12>); break;
+    switch (nrt) {   // DL = ceil(12 SPT Kp / (64 WPB)) digit loads per thread and tile
+      case 1: go(k_bgemm<1, 4, 2, 2, 4>); break;
+      case 2: go(k_bgemm<2, 4, 3, 2, 4>); break;
+      case 3: go(k_bgemm<2, 4, 3, 2, 8>); break;
+      case 4: go(k_bgemm<2, 4, 3, 2, 8>); break;
+      case 5: go(k_bgemm<2, 4, 4, 2, 8>); break;
+      case 6: go(k_bgemm<2, 4, 3, 1, 8>); break;
+      case 7: go(k_bgemm<2, 4, 3, 1, 8>); break;
+      case 8: go(k_bgemm<2, 4, 3, 1, 8>); break;
     }
   }
   hipLaunchKernelGGL(k_bcount, dim3(kCompactBlocks), dim3(1024), 0, s, g.ngroups(), b, nrt);
