@@ -482,30 +482,37 @@ __global__ __launch_bounds__(256) void k_baxpy(Geom g, BatchBufs b, int smax, in
       for (int sl = 0; sl < kCS; ++sl) acc[rt][r][sl] = v4i{0, 0, 0, 0};
   uint32_t* xw = xs[wv];
   const int kb = lane >> 4, m = lane & 15;
-  for (int qd = q0; qd < q1; ++qd) {
-    // this lane's column: union entry 64 qd + lane (past the count it re-reads the
-    // last entry; the digits there are zero)
-    const int el = 4 * qd + kb;                           // virtual group of the A operand
+  const int nvg = (count + 15) / 16;                    // virtual groups with digits
+  // Loads of one 64-column step: this lane's rows of union entry 64 qd + lane (past
+  // the count it re-reads the last entry) and the A operand, the digits of (rhs
+  // r*16 + m, virtual group 4 qd + kb) (past the last virtual group it re-reads
+  // the last one and zeroes it).  All loads are unconditional; the next step's
+  // are issued before this step's MFMAs.
+  auto fetch = [&](int qd, uint4 (&xv)[RT], v4i (&af)[NRT][kCS]) {
     const int il = 64 * qd + lane < count ? 64 * qd + lane : count - 1;
     const int64_t jl = b.list[il];
     const uint8_t* src = g.seg(jl, ch) + roff;
-    uint4 xv[RT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) xv[rt] = *reinterpret_cast<const uint4*>(src + 16 * rt);
-    // A operand: digits of (rhs r*16 + m, group el), 16 columns
-    v4i af[NRT][kCS];
+    const int el = 4 * qd + kb;
+    const bool live = el < nvg;
+    const int64_t ec = live ? el : nvg - 1;
 #pragma unroll
     for (int r = 0; r < NRT; ++r)
 #pragma unroll
       for (int sl = 0; sl < kCS; ++sl) {
-        if (16 * el < count) {
-          const uint4 v = *reinterpret_cast<const uint4*>(
-              b.bd + (((int64_t)el * Kp + r * 16 + m) * kCS + sl) * kGroup);
-          af[r][sl] = v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
-        } else {
-          af[r][sl] = v4i{0, 0, 0, 0};
-        }
+        const uint4 v = *reinterpret_cast<const uint4*>(
+            b.bd + (((int64_t)ec * Kp + r * 16 + m) * kCS + sl) * kGroup);
+        af[r][sl] = live ? v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w} : v4i{0, 0, 0, 0};
       }
+  };
+  uint4 xv[RT];
+  v4i af[NRT][kCS];
+  if (q0 < q1) fetch(q0, xv, af);
+  for (int qd = q0; qd < q1; ++qd) {
+    uint4 xn[RT];
+    v4i an[NRT][kCS];
+    fetch(qd + 1 < q1 ? qd + 1 : qd, xn, an);
     // stage: column `lane` at xw[lane * kXStride / 4 ...], rows 0 .. 16 RT - 1
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
@@ -532,6 +539,12 @@ __global__ __launch_bounds__(256) void k_baxpy(Geom g, BatchBufs b, int smax, in
           acc[rt][r][sl] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[r][sl], bf, acc[rt][r][sl], 0, 0, 0);
     }
     __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) xv[rt] = xn[rt];
+#pragma unroll
+    for (int r = 0; r < NRT; ++r)
+#pragma unroll
+      for (int sl = 0; sl < kCS; ++sl) af[r][sl] = an[r][sl];
   }
   // lane holds C[rhs = r*16 + 4 kb + i][row = rw + 16 rt + m]
 #pragma unroll
