@@ -13,6 +13,9 @@
 // theta to 7S-1 bits below c_k (S = 3: 2^-20 c_k), instead of FP32 accumulation
 // error.  The sparse products X~ B, the prox maps and the dual steps follow the
 // single right-hand-side kernels.
+#include <utility>
+
+
 #include "pqr_kernels.h"
 
 namespace pqr {
@@ -74,24 +77,35 @@ __global__ void k_bdsum(BatchBufs b, int nblk, int Kp) {
 // groups over all rows and TW right-hand-side tiles (16 k each): per 64-row
 // step it loads one A fragment per group straight from the blocked store (lane:
 // column lane % 16, rows 16 (lane / 16) .. +15 of the step, 16 contiguous bytes)
-// and one B fragment per (tile, slice) of the digits, and issues GW * TW * S
-// MFMAs.  With more than TW tiles, the block's wavefronts split the tiles of the
-// same groups (their A loads meet in the caches; HBM reads X once).  The next
-// step's fragments are loaded before this step's MFMAs; no LDS, no barriers.
+// and one B fragment per (tile, slice) of the digits (staged per block in LDS),
+// and issues GW * TW * S MFMAs.  With more than TW tiles, the block's wavefronts
+// split the tiles of the same groups (their A loads meet in the caches; HBM
+// reads X once).  A fragments are loaded NS - 1 steps ahead of their MFMAs.
 // Epilogue: the weighted soft threshold of eq. beta_update for every (column,
 // k) and per (group, tile) a 16-bit mask of the columns nonzero for some k.
 // ---------------------------------------------------------------------------
 // LDS bytes per digit row of a tile of 64 SPT rows (+16: bank spread)
 template <int SPT> constexpr int drow_bytes() { return 64 * SPT + 16; }
 
-// SPT = 64-row steps per digit tile: 2 (one barrier per 128 rows) or, where two
-// tiles of every right-hand side would not leave LDS for two blocks per CU, 1.
-// WPB = wavefronts per block: 4, or 8 when several wavefronts share a group set
-// (more groups per block share each staged digit tile).
-template <int TW, int GW, int DL, int SPT, int WPB>
-__global__ __launch_bounds__(64 * WPB, 2) void k_bgemm(Geom g, BatchBufs b, int Kp, int wps) {
+constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
+// a loop body of L steps never runs past the end: the steps of a column come in
+// chunks of 16
+template <int L> constexpr bool kStepsDivide() { return 16 % L == 0; }
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F> __device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// SPT = 64-row steps per digit tile (one barrier per tile); WPB = wavefronts per
+// block (all of them share each staged digit tile); NS = A fragment sets in flight.
+// The column groups of block bi over all rows.
+template <int TW, int GW, int DL, int SPT, int WPB, int NS>
+__device__ __forceinline__ void bgemm_pass(const Geom& g, const BatchBufs& b, int Kp, int wps,
+                                           int64_t bi, uint8_t* dtile) {
   constexpr int kDRow = drow_bytes<SPT>();
-  extern __shared__ __attribute__((aligned(16))) uint8_t dtile[];   // 2 x S*Kp x kDRow
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const int nrt = Kp / 16;
@@ -99,7 +113,7 @@ __global__ __launch_bounds__(64 * WPB, 2) void k_bgemm(Geom g, BatchBufs b, int 
   // wps wavefronts share one set of GW groups; wavefront wv % wps takes tiles r0..
   // A wavefront past the last group or tile still runs the loop (it takes part in
   // the digit tiles and the barriers) on clamped indices and skips the epilogue.
-  const int64_t gw0r = ((int64_t)blockIdx.x * (WPB / wps) + wv / wps) * GW;
+  const int64_t gw0r = (bi * (WPB / wps) + wv / wps) * GW;
   const int r0r = (wv % wps) * TW;
   const bool wave_live = gw0r < ng && r0r < nrt;
   const int64_t gw0 = gw0r < ng ? gw0r : ng - 1;
@@ -113,7 +127,7 @@ __global__ __launch_bounds__(64 * WPB, 2) void k_bgemm(Geom g, BatchBufs b, int 
 #pragma unroll
       for (int s = 0; s < kBS; ++s) acc[q][r][s] = v4i{0, 0, 0, 0};
   const int64_t nsteps = g.nchunks() * 16;   // 64-row steps (1024-row chunks)
-  const int64_t nsup = nsteps / 2;           // 128-row digit tiles
+  const int64_t nsup = nsteps / SPT;         // digit tiles of 64 SPT rows
   const bool tile_ok[2] = {true, TW > 1 && r0 + 1 < nrt};
   // Buffer loads: a lane's offset is fixed (one VGPR per fragment), the step's
   // part is a wave-uniform SGPR offset; no per-step address arithmetic.
@@ -183,63 +197,45 @@ __global__ __launch_bounds__(64 * WPB, 2) void k_bgemm(Geom g, BatchBufs b, int 
         for (int s = 0; s < kBS; ++s)
           acc[q][r][s] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[q], bf[r][s], acc[q][r][s], 0, 0, 0);
   };
-  // Two A fragment sets in ping-pong (steps 2u and 2u + 1 of digit tile u): a set
-  // is reloaded for the next tile right after its MFMAs issue, so the other set's
-  // loads are in flight while these MFMAs run.  The next digit tile is loaded at
-  // the top of a tile and stored to the other LDS buffer at its end; one barrier
-  // per tile.  Scheduling barriers keep this order; loads past the end re-read
-  // the last tile (in bounds).
-  v4i aS[2][GW], bf[TW][kBS];
+  // NS A fragment sets in rotation: step t uses set t % NS, and right after its
+  // MFMAs issue the set is reloaded for step t + NS, so NS - 1 steps' loads are in
+  // flight while these MFMAs run.  The next digit tile is loaded at the top of a
+  // tile and stored to the other LDS buffer at its end; one barrier per tile.
+  // Scheduling barriers keep this order; loads past the end re-read the last step
+  // or tile (in bounds).  The loop body is L = lcm(NS, SPT) steps, unrolled so that
+  // the set and the step within the tile are compile-time constants.
+  constexpr int L = NS * SPT / gcd_c(NS, SPT);
+  v4i aS[NS][GW], bf[TW][kBS];
   v4u dr[DL];
   load_d(0, dr);
   store_d(0, dr);
   __syncthreads();
-  load_a(0, aS[0]);
-  __builtin_amdgcn_sched_barrier(0);   // set 0 strictly older than set 1 on entry
-  load_a(1, aS[1]);
-  __builtin_amdgcn_sched_barrier(0);
-  if constexpr (SPT == 2) {
-    for (int64_t u = 0; u < nsup; ++u) {
+  static_for<NS>([&](auto I) {   // each set strictly older than the next on entry
+    load_a(I.value < nsteps ? I.value : nsteps - 1, aS[I.value]);
+    __builtin_amdgcn_sched_barrier(0);
+  });
+  for (int64_t t0 = 0; t0 < nsteps; t0 += L) {
+    static_for<L>([&](auto I) {
+      constexpr int set = I.value % NS, h = I.value % SPT;
+      const int64_t t = t0 + I.value;
+      const int64_t u = t / SPT;   // digit tile
       const int buf = (int)(u & 1);
-      load_d(u + 1 < nsup ? u + 1 : u, dr);
+      if constexpr (h == 0) {
+        load_d(u + 1 < nsup ? u + 1 : nsup - 1, dr);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (kStepsDivide<L>() || t < nsteps) {   // wave-uniform
+        read_b(buf, h, bf);
+        mma(aS[set], bf);
+      }
       __builtin_amdgcn_sched_barrier(0);
-      read_b(buf, 0, bf);
-      mma(aS[0], bf);
+      load_a(t + NS < nsteps ? t + NS : nsteps - 1, aS[set]);
       __builtin_amdgcn_sched_barrier(0);
-      const int64_t t2 = 2 * u + 2 < nsteps ? 2 * u + 2 : nsteps - 2;
-      load_a(t2, aS[0]);
-      __builtin_amdgcn_sched_barrier(0);
-      read_b(buf, 1, bf);
-      mma(aS[1], bf);
-      __builtin_amdgcn_sched_barrier(0);
-      load_a(t2 + 1, aS[1]);
-      __builtin_amdgcn_sched_barrier(0);
-      store_d(buf ^ 1, dr);
-      __syncthreads();
-    }
-  } else {
-    // one 64-row tile per step: step t reads LDS buffer t & 1 (t even: 0)
-    for (int64_t t = 0; t < nsteps; t += 2) {
-      load_d(t + 1, dr);
-      __builtin_amdgcn_sched_barrier(0);
-      read_b(0, 0, bf);
-      mma(aS[0], bf);
-      __builtin_amdgcn_sched_barrier(0);
-      const int64_t t2 = t + 2 < nsteps ? t + 2 : nsteps - 2;
-      load_a(t2, aS[0]);
-      __builtin_amdgcn_sched_barrier(0);
-      store_d(1, dr);
-      __syncthreads();
-      load_d(t + 2 < nsteps ? t + 2 : t + 1, dr);
-      __builtin_amdgcn_sched_barrier(0);
-      read_b(1, 0, bf);
-      mma(aS[1], bf);
-      __builtin_amdgcn_sched_barrier(0);
-      load_a(t2 + 1, aS[1]);
-      __builtin_amdgcn_sched_barrier(0);
-      store_d(0, dr);
-      __syncthreads();
-    }
+      if constexpr (h == SPT - 1) {
+        store_d(buf ^ 1, dr);
+        __syncthreads();
+      }
+    });
   }
   if (!wave_live) return;
   // epilogue: lane holds columns 4*kq + e (e = 0..3) of each group for rhs (r0+r)*16 + col
@@ -282,6 +278,12 @@ __global__ __launch_bounds__(64 * WPB, 2) void k_bgemm(Geom g, BatchBufs b, int 
       if (lane == 0) b.mask[grp * nrt + r0 + r] = cmask;
     }
   }
+}
+
+template <int TW, int GW, int DL, int SPT, int WPB, int NS>
+__global__ __launch_bounds__(64 * WPB, 2) void k_bgemm(Geom g, BatchBufs b, int Kp, int wps) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t dtile[];   // 2 x S*Kp x 64 SPT (+16)
+  bgemm_pass<TW, GW, DL, SPT, WPB, NS>(g, b, Kp, wps, blockIdx.x, dtile);
 }
 
 // ---------------------------------------------------------------------------
@@ -633,6 +635,26 @@ __global__ void k_bfinal(BatchBufs b, int nblk, int Kp) {
   b.norms[k * 4 + 2] = s4;
 }
 
+// One k_bgemm launch: groups per block = (WPB / wps) GW, two digit tiles of LDS.
+// The block's threads stage every digit row of a tile: 64 WPB DL >= 3 Kp * 4 SPT.
+template <int TW, int GW, int DL, int SPT, int WPB, int NS>
+static hipError_t launch_bgemm(const Geom& g, const BatchBufs& b, int Kp, int wps, hipStream_t s,
+                               hipEvent_t ev0, hipEvent_t ev1) {
+  if (64 * WPB * DL < kBS * Kp * 4 * SPT || WPB % wps || Kp > 16 * TW * wps)
+    return hipErrorInvalidValue;
+  auto kern = k_bgemm<TW, GW, DL, SPT, WPB, NS>;
+  const size_t lds = (size_t)2 * kBS * Kp * drow_bytes<SPT>();
+  const int64_t per_block = (int64_t)(WPB / wps) * GW;
+  const dim3 grid((unsigned)((g.ngroups() + per_block - 1) / per_block));
+  // allow more than 64 KB of dynamic LDS for this kernel (a cheap host call)
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (ev0) (void)hipEventRecord(ev0, s);
+  hipLaunchKernelGGL(kern, grid, dim3(64 * WPB), lds, s, g, b, Kp, wps);
+  if (ev1) (void)hipEventRecord(ev1, s);
+  return hipSuccess;
+}
+
 // ---------------------------------------------------------------------------
 hipError_t launch_batch_iteration(const Geom& g, const BatchBufs& b, int Kp, double mu,
                                   double sigma, double eta0, int smax, int min_per,
@@ -642,34 +664,24 @@ hipError_t launch_batch_iteration(const Geom& g, const BatchBufs& b, int Kp, dou
   const int nrt = Kp / 16;
   hipLaunchKernelGGL(k_bdigits, dim3(nb, Kp), dim3(256), 0, s, b, g.n, g.n_pad, Kp);
   hipLaunchKernelGGL(k_bdsum, dim3(1), dim3(128), 0, s, b, (int)nb, Kp);
-  // one or two tiles per wavefront, GW = 4 groups (GW * TW * S * 4 <= 96 accumulators);
-  // wps = wavefronts sharing a set of groups (1, 2 or 4); LDS: two digit tiles
-  {
-    const bool small_tiles = nrt >= 6;   // 2 x 3 Kp x 144 bytes would leave one block per CU
-    const size_t lds = (size_t)2 * kBS * Kp * (small_tiles ? drow_bytes<1>() : drow_bytes<2>());
-    const int wps = nrt <= 2 ? 1 : (nrt <= 4 ? 2 : 4);
-    const int wpb = wps >= 2 ? 8 : 4;
-    const int64_t per_block = (int64_t)(wpb / wps) * 4;   // groups per block (GW = 4)
-    const dim3 grid((unsigned)((g.ngroups() + per_block - 1) / per_block));
-    auto go = [&](auto kern) {
-      // allow more than 64 KB of dynamic LDS for this kernel (a cheap host call)
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-      if (ev0) (void)hipEventRecord(ev0, s);
-      hipLaunchKernelGGL(kern, grid, dim3(64 * wpb), lds, s, g, b, Kp, wps);
-      if (ev1) (void)hipEventRecord(ev1, s);
-    };
-    switch (nrt) {   // DL = ceil(12 SPT Kp / (64 WPB)) digit loads per thread and tile
-      case 1: go(k_bgemm<1, 4, 2, 2, 4>); break;
-      case 2: go(k_bgemm<2, 4, 3, 2, 4>); break;
-      case 3: go(k_bgemm<2, 4, 3, 2, 8>); break;
-      case 4: go(k_bgemm<2, 4, 3, 2, 8>); break;
-      case 5: go(k_bgemm<2, 4, 4, 2, 8>); break;
-      case 6: go(k_bgemm<2, 4, 3, 1, 8>); break;
-      case 7: go(k_bgemm<2, 4, 3, 1, 8>); break;
-      case 8: go(k_bgemm<2, 4, 3, 1, 8>); break;
-    }
+  // One or two tiles per wavefront, GW = 4 groups (GW * TW * S * 4 <= 96 accumulators);
+  // wps = wavefronts sharing a set of groups (1, 2 or 4).  Blocks of 8 wavefronts:
+  // at about 200 VGPRs one block fills a CU, so two digit tiles of up to 128 KB of
+  // LDS cost no occupancy, and a staged tile serves 8 GW / wps groups.  Digit tiles
+  // of 256 rows for 3 to 5 tiles, else 128 rows (faster for 1 or 2 tiles; LDS
+  // for 6 to 8).
+  hipError_t e = hipSuccess;
+  switch (nrt) {   // DL = ceil(12 SPT Kp / (64 WPB)) digit loads per thread and tile
+    case 1: e = launch_bgemm<1, 4, 1, 2, 8, 2>(g, b, Kp, 1, s, ev0, ev1); break;
+    case 2: e = launch_bgemm<2, 4, 2, 2, 8, 2>(g, b, Kp, 1, s, ev0, ev1); break;
+    case 3: e = launch_bgemm<2, 4, 6, 4, 8, 2>(g, b, Kp, 2, s, ev0, ev1); break;
+    case 4: e = launch_bgemm<2, 4, 6, 4, 8, 2>(g, b, Kp, 2, s, ev0, ev1); break;
+    case 5: e = launch_bgemm<2, 4, 8, 4, 8, 2>(g, b, Kp, 4, s, ev0, ev1); break;
+    case 6: e = launch_bgemm<2, 4, 6, 2, 8, 2>(g, b, Kp, 4, s, ev0, ev1); break;
+    case 7: e = launch_bgemm<2, 4, 6, 2, 8, 2>(g, b, Kp, 4, s, ev0, ev1); break;
+    case 8: e = launch_bgemm<2, 4, 6, 2, 8, 2>(g, b, Kp, 4, s, ev0, ev1); break;
   }
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_bcount, dim3(kCompactBlocks), dim3(1024), 0, s, g.ngroups(), b, nrt);
   hipLaunchKernelGGL(k_bscatter, dim3(kCompactBlocks), dim3(1024), 0, s, g.ngroups(), b, nrt,
                      eta0, Kp);
