@@ -13,6 +13,7 @@
 // theta to 7S-1 bits below c_k (S = 3: 2^-20 c_k), instead of FP32 accumulation
 // error.  The sparse products X~ B, the prox maps and the dual steps follow the
 // single right-hand-side kernels.
+#include <climits>
 #include <utility>
 
 
@@ -101,10 +102,12 @@ template <int N, class F> __device__ __forceinline__ void static_for(F&& f) {
 
 // SPT = 64-row steps per digit tile (one barrier per tile); WPB = wavefronts per
 // block (all of them share each staged digit tile); NS = A fragment sets in flight.
-// The column groups of block bi over all rows.
-template <int TW, int GW, int DL, int SPT, int WPB, int NS>
-__device__ __forceinline__ void bgemm_pass(const Geom& g, const BatchBufs& b, int Kp, int wps,
-                                           int64_t bi, uint8_t* dtile) {
+// S = digit slices; CERT selects the certificate epilogue (per (group set, k)
+// maxima of |x~_j^T theta_q| / (lambda_k w_j)) over the iteration's (eq.
+// beta_update and the column masks).  The column groups of block bi over all rows.
+template <int TW, int GW, int DL, int SPT, int WPB, int NS, int S, bool CERT>
+__device__ __forceinline__ void bgemm_pass(const Geom& g, const BatchBufs& b, const CertArgs& ca,
+                                           int Kp, int wps, int64_t bi, uint8_t* dtile) {
   constexpr int kDRow = drow_bytes<SPT>();
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
@@ -119,13 +122,13 @@ __device__ __forceinline__ void bgemm_pass(const Geom& g, const BatchBufs& b, in
   const int64_t gw0 = gw0r < ng ? gw0r : ng - 1;
   const int r0 = r0r < nrt ? r0r : nrt - 1;
   const int col = lane & 15, kq = lane >> 4;
-  v4i acc[GW][TW][kBS];
+  v4i acc[GW][TW][S];
 #pragma unroll
   for (int q = 0; q < GW; ++q)
 #pragma unroll
     for (int r = 0; r < TW; ++r)
 #pragma unroll
-      for (int s = 0; s < kBS; ++s) acc[q][r][s] = v4i{0, 0, 0, 0};
+      for (int s = 0; s < S; ++s) acc[q][r][s] = v4i{0, 0, 0, 0};
   const int64_t nsteps = g.nchunks() * 16;   // 64-row steps (1024-row chunks)
   const int64_t nsup = nsteps / SPT;         // digit tiles of 64 SPT rows
   const bool tile_ok[2] = {true, TW > 1 && r0 + 1 < nrt};
@@ -156,10 +159,10 @@ __device__ __forceinline__ void bgemm_pass(const Geom& g, const BatchBufs& b, in
   // block in LDS (row s*Kp + k: 64 SPT bytes), double-buffered; a wavefront reads
   // its fragments there (rhs (r0 + r)*16 + col, bytes 64 h + 16 kq of step h).
   constexpr int kParts = 4 * SPT;                  // 16-byte pieces per digit row
-  const int drows = kBS * Kp, total16 = drows * kParts;
+  const int drows = S * Kp, total16 = drows * kParts;
   const int64_t dbytes = (int64_t)drows * g.n_pad;
   const __amdgpu_buffer_rsrc_t brsrc = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)b.dig, (short)0, (int)(dbytes < 0x7fffffffll ? dbytes : 0x7fffffffll), 0x00020000);
+      (void*)(CERT ? ca.dig : b.dig), (short)0, (int)(dbytes < 0x7fffffffll ? dbytes : 0x7fffffffll), 0x00020000);
   auto load_d = [&](int64_t u, v4u (&dr)[DL]) {
 #pragma unroll
     for (int i = 0; i < DL; ++i) {
@@ -178,23 +181,23 @@ __device__ __forceinline__ void bgemm_pass(const Geom& g, const BatchBufs& b, in
                                 (idx % kParts) * 16) = dr[i];
     }
   };
-  auto read_b = [&](int buf, int h, v4i (&bf)[TW][kBS]) {
+  auto read_b = [&](int buf, int h, v4i (&bf)[TW][S]) {
 #pragma unroll
     for (int r = 0; r < TW; ++r)
 #pragma unroll
-      for (int s = 0; s < kBS; ++s) {
+      for (int s = 0; s < S; ++s) {
         const int row = s * Kp + (r0 + (tile_ok[r] ? r : 0)) * 16 + col;
         bf[r][s] = *reinterpret_cast<const v4i*>(dtile + ((int64_t)buf * drows + row) * kDRow +
                                                  h * 64 + kq * 16);
       }
   };
-  auto mma = [&](const v4i (&af)[GW], const v4i (&bf)[TW][kBS]) {
+  auto mma = [&](const v4i (&af)[GW], const v4i (&bf)[TW][S]) {
 #pragma unroll
     for (int q = 0; q < GW; ++q)
 #pragma unroll
       for (int r = 0; r < TW; ++r)
 #pragma unroll
-        for (int s = 0; s < kBS; ++s)
+        for (int s = 0; s < S; ++s)
           acc[q][r][s] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[q], bf[r][s], acc[q][r][s], 0, 0, 0);
   };
   // NS A fragment sets in rotation: step t uses set t % NS, and right after its
@@ -205,7 +208,7 @@ __device__ __forceinline__ void bgemm_pass(const Geom& g, const BatchBufs& b, in
   // or tile (in bounds).  The loop body is L = lcm(NS, SPT) steps, unrolled so that
   // the set and the step within the tile are compile-time constants.
   constexpr int L = NS * SPT / gcd_c(NS, SPT);
-  v4i aS[NS][GW], bf[TW][kBS];
+  v4i aS[NS][GW], bf[TW][S];
   v4u dr[DL];
   load_d(0, dr);
   store_d(0, dr);
@@ -238,52 +241,88 @@ __device__ __forceinline__ void bgemm_pass(const Geom& g, const BatchBufs& b, in
     });
   }
   if (!wave_live) return;
-  // epilogue: lane holds columns 4*kq + e (e = 0..3) of each group for rhs (r0+r)*16 + col
+  if constexpr (CERT) {
+    // lane: columns 4 kq + e of each group for k = (r0 + r) 16 + col; exact
+    // P = x_j^T T_k (sum T_k = 0, so no mean term), v = P unit_k / s_j
+    const int64_t gs = gw0r / GW;
+    const int64_t ngs = (ng + GW - 1) / GW;
 #pragma unroll
-  for (int r = 0; r < TW; ++r) {
-    if (!tile_ok[r]) break;
-    const int k = (r0 + r) * 16 + col;
-    const bool live = k < b.K && b.kact[k] != 0;   // frozen: beta kept, out of the union
-    const double unit = live ? b.scale[k] / (double)(1 << (7 * kBS - 1)) : 0.0;
-    const double tq = live ? (double)b.tsumq[k] : 0.0;
-    const float lamk = live ? b.lam[k] : 0.f;
+    for (int r = 0; r < TW; ++r) {
+      if (!tile_ok[r]) break;
+      const int k = (r0 + r) * 16 + col;
+      const bool live = k < ca.K;
+      const double unit = live ? ca.unit[k] : 0.0;
+      const double lamk = live ? ca.lam[k] : 1.0;
+      double m = 0.0;
 #pragma unroll
-    for (int q = 0; q < GW; ++q) {
-      const int64_t grp = gw0 + q;
-      if (grp >= ng) break;
-      const float eta = b.geta[grp];
-      uint32_t cmask = 0;   // bit c: column c of the group is nonzero for some k of the tile
+      for (int q = 0; q < GW; ++q) {
+        const int64_t grp = gw0 + q;
+        if (grp >= ng) break;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t j = grp * kGroup + 4 * kq + e;
-        long long P = 0;
+        for (int e = 0; e < 4; ++e) {
+          const int64_t j = grp * kGroup + 4 * kq + e;
+          if (j >= g.p) continue;
+          long long P = 0;
 #pragma unroll
-        for (int s = 0; s < kBS; ++s) P = P * 128 + (long long)acc[q][r][s][e];
-        // x~_j^T theta_k = (x_j^T theta_k - m_j sum theta_k) / s_j in the quantised theta
-        const double v = ((double)P - (double)b.cm[j] * tq) * unit * (double)b.cinv[j];
-        float* bp = b.beta + (int64_t)k * g.p_pad + j;
-        if (live) {
-          const float bo = *bp;
-          const float lj = lamk * b.w[j];
-          const float a = eta * bo + (float)v;
-          const float bn = (fmaxf(a - lj, 0.f) - fmaxf(-a - lj, 0.f)) / eta;   // eq. beta_update
-          *bp = bn;
+          for (int sl = 0; sl < S; ++sl) P = P * 128 + (long long)acc[q][r][sl][e];
+          const double v = (double)P * unit * ca.cinv[j];
+          m = fmax(m, fabs(v) / (lamk * ca.w[j]));
         }
-        // lanes 16 kq .. 16 kq + 15 hold column 4 kq + e for the tile's 16 k
-        const unsigned long long bal = __ballot(live && *bp != 0.f);
-#pragma unroll
-        for (int h = 0; h < 4; ++h)
-          cmask |= (((bal >> (16 * h)) & 0xffffull) != 0ull ? 1u : 0u) << (4 * h + e);
       }
-      if (lane == 0) b.mask[grp * nrt + r0 + r] = cmask;
+      // lanes col + 16 h (h = 0..3) hold the same k
+      m = fmax(m, __shfl_xor(m, 16));
+      m = fmax(m, __shfl_xor(m, 32));
+      if (kq == 0 && live) ca.gmax[(int64_t)k * ngs + gs] = m;
+    }
+  } else {
+    // epilogue: lane holds columns 4*kq + e (e = 0..3) of each group for rhs (r0+r)*16 + col
+#pragma unroll
+    for (int r = 0; r < TW; ++r) {
+      if (!tile_ok[r]) break;
+      const int k = (r0 + r) * 16 + col;
+      const bool live = k < b.K && b.kact[k] != 0;   // frozen: beta kept, out of the union
+      const double unit = live ? b.scale[k] / (double)(1 << (7 * S - 1)) : 0.0;
+      const double tq = live ? (double)b.tsumq[k] : 0.0;
+      const float lamk = live ? b.lam[k] : 0.f;
+#pragma unroll
+      for (int q = 0; q < GW; ++q) {
+        const int64_t grp = gw0 + q;
+        if (grp >= ng) break;
+        const float eta = b.geta[grp];
+        uint32_t cmask = 0;   // bit c: column c of the group is nonzero for some k of the tile
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t j = grp * kGroup + 4 * kq + e;
+          long long P = 0;
+#pragma unroll
+          for (int s = 0; s < S; ++s) P = P * 128 + (long long)acc[q][r][s][e];
+          // x~_j^T theta_k = (x_j^T theta_k - m_j sum theta_k) / s_j in the quantised theta
+          const double v = ((double)P - (double)b.cm[j] * tq) * unit * (double)b.cinv[j];
+          float* bp = b.beta + (int64_t)k * g.p_pad + j;
+          if (live) {
+            const float bo = *bp;
+            const float lj = lamk * b.w[j];
+            const float a = eta * bo + (float)v;
+            const float bn = (fmaxf(a - lj, 0.f) - fmaxf(-a - lj, 0.f)) / eta;   // eq. beta_update
+            *bp = bn;
+          }
+          // lanes 16 kq .. 16 kq + 15 hold column 4 kq + e for the tile's 16 k
+          const unsigned long long bal = __ballot(live && *bp != 0.f);
+#pragma unroll
+          for (int h = 0; h < 4; ++h)
+            cmask |= (((bal >> (16 * h)) & 0xffffull) != 0ull ? 1u : 0u) << (4 * h + e);
+        }
+        if (lane == 0) b.mask[grp * nrt + r0 + r] = cmask;
+      }
     }
   }
 }
 
-template <int TW, int GW, int DL, int SPT, int WPB, int NS>
-__global__ __launch_bounds__(64 * WPB, 2) void k_bgemm(Geom g, BatchBufs b, int Kp, int wps) {
+template <int TW, int GW, int DL, int SPT, int WPB, int NS, int S, bool CERT>
+__global__ __launch_bounds__(64 * WPB, 2) void k_bgemm(Geom g, BatchBufs b, CertArgs ca, int Kp,
+                                                       int wps) {
   extern __shared__ __attribute__((aligned(16))) uint8_t dtile[];   // 2 x S*Kp x 64 SPT (+16)
-  bgemm_pass<TW, GW, DL, SPT, WPB, NS>(g, b, Kp, wps, blockIdx.x, dtile);
+  bgemm_pass<TW, GW, DL, SPT, WPB, NS, S, CERT>(g, b, ca, Kp, wps, blockIdx.x, dtile);
 }
 
 // ---------------------------------------------------------------------------
@@ -636,23 +675,138 @@ __global__ void k_bfinal(BatchBufs b, int nblk, int Kp) {
 }
 
 // One k_bgemm launch: groups per block = (WPB / wps) GW, two digit tiles of LDS.
-// The block's threads stage every digit row of a tile: 64 WPB DL >= 3 Kp * 4 SPT.
-template <int TW, int GW, int DL, int SPT, int WPB, int NS>
-static hipError_t launch_bgemm(const Geom& g, const BatchBufs& b, int Kp, int wps, hipStream_t s,
-                               hipEvent_t ev0, hipEvent_t ev1) {
-  if (64 * WPB * DL < kBS * Kp * 4 * SPT || WPB % wps || Kp > 16 * TW * wps)
+// The block's threads stage every digit row of a tile: 64 WPB DL >= S Kp * 4 SPT.
+template <int TW, int GW, int DL, int SPT, int WPB, int NS, int S, bool CERT>
+static hipError_t launch_bgemm(const Geom& g, const BatchBufs& b, const CertArgs& ca, int Kp,
+                               int wps, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  if (64 * WPB * DL < S * Kp * 4 * SPT || WPB % wps || Kp > 16 * TW * wps)
     return hipErrorInvalidValue;
-  auto kern = k_bgemm<TW, GW, DL, SPT, WPB, NS>;
-  const size_t lds = (size_t)2 * kBS * Kp * drow_bytes<SPT>();
+  auto kern = k_bgemm<TW, GW, DL, SPT, WPB, NS, S, CERT>;
+  const size_t lds = (size_t)2 * S * Kp * drow_bytes<SPT>();
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
   const int64_t per_block = (int64_t)(WPB / wps) * GW;
   const dim3 grid((unsigned)((g.ngroups() + per_block - 1) / per_block));
   // allow more than 64 KB of dynamic LDS for this kernel (a cheap host call)
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   if (ev0) (void)hipEventRecord(ev0, s);
-  hipLaunchKernelGGL(kern, grid, dim3(64 * WPB), lds, s, g, b, Kp, wps);
+  hipLaunchKernelGGL(kern, grid, dim3(64 * WPB), lds, s, g, b, ca, Kp, wps);
   if (ev1) (void)hipEventRecord(ev1, s);
   return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// Exact-integer certificate (batched right-hand sides).  The dual point is
+// theta_q = unit T, T integer: a point of the dual feasible set of the
+// Lagrangian dual (box, zero sum) whose products x~_j^T theta_q the int8 matrix
+// cores give exactly, so the only rounding left is in the final FP64 scalings.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_cquant(const double* __restrict__ tp, int64_t n,
+                                                 int64_t n_pad, double tau, double unit,
+                                                 const double* __restrict__ y, int* tq, int8_t* dig,
+                                                 int kc, int Kc, double* out) {
+  __shared__ long long rs[16], rmx[16], rmn[16];
+  __shared__ int rmxi[16], rmni[16];
+  __shared__ double rd[16];
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  // box in steps: Tlo = ceil(((tau - 1) / n) / unit), Thi = floor((tau / n) / unit)
+  const long long Tlo = (long long)ceil(((tau - 1.0) / (double)n) / unit);
+  const long long Thi = (long long)floor((tau / (double)n) / unit);
+  long long sum = 0, mx = LLONG_MIN, mn = LLONG_MAX;
+  int mxi = 0, mni = 0;
+  for (int64_t i = t; i < n; i += 1024) {
+    long long T = (long long)(tp[i] / unit);   // truncation toward zero
+    T = T > Thi ? Thi : (T < Tlo ? Tlo : T);
+    tq[i] = (int)T;
+    sum += T;
+    if (T > mx) { mx = T; mxi = (int)i; }   // first index of the maximum (i increases)
+    if (T < mn) { mn = T; mni = (int)i; }
+  }
+  // wavefront reductions (ties: smallest index)
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    sum += __shfl_xor(sum, off);
+    const long long omx = __shfl_xor(mx, off), omn = __shfl_xor(mn, off);
+    const int omxi = __shfl_xor(mxi, off), omni = __shfl_xor(mni, off);
+    if (omx > mx || (omx == mx && omxi < mxi)) { mx = omx; mxi = omxi; }
+    if (omn < mn || (omn == mn && omni < mni)) { mn = omn; mni = omni; }
+  }
+  if (lane == 0) { rs[wid] = sum; rmx[wid] = mx; rmn[wid] = mn; rmxi[wid] = mxi; rmni[wid] = mni; }
+  __syncthreads();
+  if (t == 0) {
+    long long S0 = 0, M = LLONG_MIN, N = LLONG_MAX;
+    int Mi = 0, Ni = 0;
+    for (int w = 0; w < 16; ++w) {
+      S0 += rs[w];
+      if (rmx[w] > M || (rmx[w] == M && rmxi[w] < Mi)) { M = rmx[w]; Mi = rmxi[w]; }
+      if (rmn[w] < N || (rmn[w] == N && rmni[w] < Ni)) { N = rmn[w]; Ni = rmni[w]; }
+    }
+    double status = 0.0;
+    if (S0 > 0) {
+      if (M - S0 >= Tlo) tq[Mi] = (int)(M - S0); else status = 1.0;
+    } else if (S0 < 0) {
+      if (N - S0 <= Thi) tq[Ni] = (int)(N - S0); else status = 1.0;
+    }
+    out[7] = status;
+  }
+  __threadfence_block();
+  __syncthreads();
+  // digits and y^T theta_q
+  double q[1] = {0.0};
+  for (int64_t i = t; i < n_pad; i += 1024) {
+    long long rest = i < n ? (long long)tq[i] : 0;
+    if (i < n) q[0] += y[i] * (double)rest;
+#pragma unroll
+    for (int sl = kCertSlices - 1; sl > 0; --sl) {
+      const long long lo = ((rest + 64) & 127) - 64;
+      dig[((int64_t)sl * Kc + kc) * n_pad + i] = (int8_t)lo;
+      rest = (rest - lo) >> 7;
+    }
+    dig[(int64_t)kc * n_pad + i] = (int8_t)rest;
+  }
+  // block sum in a fixed order
+  double v = q[0];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  if (lane == 0) rd[wid] = v;
+  __syncthreads();
+  if (t == 0) {
+    double a = 0.0;
+    for (int w = 0; w < 16; ++w) a += rd[w];
+    out[2] = a * unit;
+  }
+}
+
+hipError_t launch_cert_quantize(const double* theta_p, int64_t n, int64_t n_pad, double tau,
+                                double unit, const double* y, int* tq, int8_t* dig, int kc,
+                                int Kc, double* out, hipStream_t s) {
+  if (kc < 0 || kc >= Kc || n > 0x7fffffffll || !(unit > 0.0)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cquant, dim3(1), dim3(1024), 0, s, theta_p, n, n_pad, tau, unit, y, tq, dig,
+                     kc, Kc, out);
+  return hipGetLastError();
+}
+
+int64_t cert_group_sets(const Geom& g) { return (g.ngroups() + 3) / 4; }
+
+// GW = 4 groups per wavefront (the group sets of c.gmax); 8-wavefront blocks;
+// 4 slices hold 32 accumulator registers more than an iteration's 3, so the
+// digit tiles are shorter (at most 4 staging loads per thread, no spills).
+hipError_t launch_cert_pass(const Geom& g, const CertArgs& c, int Kc, hipStream_t s) {
+  if (g.fmt != I8 || g.rpl != 16 || Kc % 16 || Kc < 16 || Kc > 128 || c.K > Kc)
+    return hipErrorInvalidValue;
+  const BatchBufs b{};
+  constexpr int S = kCertSlices;
+  switch (Kc / 16) {   // DL = ceil(16 SPT Kc / (64 WPB))
+    case 1: return launch_bgemm<1, 4, 1, 2, 8, 2, S, true>(g, b, c, Kc, 1, s, nullptr, nullptr);
+    case 2: return launch_bgemm<2, 4, 2, 2, 8, 2, S, true>(g, b, c, Kc, 1, s, nullptr, nullptr);
+    case 3: return launch_bgemm<2, 4, 4, 2, 8, 2, S, true>(g, b, c, Kc, 2, s, nullptr, nullptr);
+    case 4: return launch_bgemm<2, 4, 4, 2, 8, 2, S, true>(g, b, c, Kc, 2, s, nullptr, nullptr);
+    case 5: return launch_bgemm<2, 4, 5, 2, 8, 2, S, true>(g, b, c, Kc, 4, s, nullptr, nullptr);
+    case 6: return launch_bgemm<2, 4, 4, 1, 8, 2, S, true>(g, b, c, Kc, 4, s, nullptr, nullptr);
+    case 7: return launch_bgemm<2, 4, 4, 1, 8, 2, S, true>(g, b, c, Kc, 4, s, nullptr, nullptr);
+    case 8: return launch_bgemm<2, 4, 4, 1, 8, 2, S, true>(g, b, c, Kc, 4, s, nullptr, nullptr);
+  }
+  return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------
@@ -672,14 +826,14 @@ hipError_t launch_batch_iteration(const Geom& g, const BatchBufs& b, int Kp, dou
   // for 6 to 8).
   hipError_t e = hipSuccess;
   switch (nrt) {   // DL = ceil(12 SPT Kp / (64 WPB)) digit loads per thread and tile
-    case 1: e = launch_bgemm<1, 4, 1, 2, 8, 2>(g, b, Kp, 1, s, ev0, ev1); break;
-    case 2: e = launch_bgemm<2, 4, 2, 2, 8, 2>(g, b, Kp, 1, s, ev0, ev1); break;
-    case 3: e = launch_bgemm<2, 4, 6, 4, 8, 2>(g, b, Kp, 2, s, ev0, ev1); break;
-    case 4: e = launch_bgemm<2, 4, 6, 4, 8, 2>(g, b, Kp, 2, s, ev0, ev1); break;
-    case 5: e = launch_bgemm<2, 4, 8, 4, 8, 2>(g, b, Kp, 4, s, ev0, ev1); break;
-    case 6: e = launch_bgemm<2, 4, 6, 2, 8, 2>(g, b, Kp, 4, s, ev0, ev1); break;
-    case 7: e = launch_bgemm<2, 4, 6, 2, 8, 2>(g, b, Kp, 4, s, ev0, ev1); break;
-    case 8: e = launch_bgemm<2, 4, 6, 2, 8, 2>(g, b, Kp, 4, s, ev0, ev1); break;
+    case 1: e = launch_bgemm<1, 4, 1, 2, 8, 2, kBS, false>(g, b, CertArgs{}, Kp, 1, s, ev0, ev1); break;
+    case 2: e = launch_bgemm<2, 4, 2, 2, 8, 2, kBS, false>(g, b, CertArgs{}, Kp, 1, s, ev0, ev1); break;
+    case 3: e = launch_bgemm<2, 4, 6, 4, 8, 2, kBS, false>(g, b, CertArgs{}, Kp, 2, s, ev0, ev1); break;
+    case 4: e = launch_bgemm<2, 4, 6, 4, 8, 2, kBS, false>(g, b, CertArgs{}, Kp, 2, s, ev0, ev1); break;
+    case 5: e = launch_bgemm<2, 4, 8, 4, 8, 2, kBS, false>(g, b, CertArgs{}, Kp, 4, s, ev0, ev1); break;
+    case 6: e = launch_bgemm<2, 4, 6, 2, 8, 2, kBS, false>(g, b, CertArgs{}, Kp, 4, s, ev0, ev1); break;
+    case 7: e = launch_bgemm<2, 4, 6, 2, 8, 2, kBS, false>(g, b, CertArgs{}, Kp, 4, s, ev0, ev1); break;
+    case 8: e = launch_bgemm<2, 4, 6, 2, 8, 2, kBS, false>(g, b, CertArgs{}, Kp, 4, s, ev0, ev1); break;
   }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_bcount, dim3(kCompactBlocks), dim3(1024), 0, s, g.ngroups(), b, nrt);

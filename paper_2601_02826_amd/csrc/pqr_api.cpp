@@ -67,6 +67,12 @@ struct pqr_ctx {
   double* cert4 = nullptr;          // 4 x n_pad projected thetas (batched certificates)
   double* out4 = nullptr;           // 4 x 8 certificate outputs
   double* gmax4 = nullptr;          // 4 x ngroups dual-ratio partials
+  int8_t* cdig = nullptr;           // exact batched certificate: 4 x 128 x n_pad digits
+  int* ctq = nullptr;               // n_pad quantised theta (scratch)
+  double* cgmax = nullptr;          // 128 x group sets dual-ratio partials
+  double* clamk = nullptr;          // 128 lambda_k of the pass
+  double* cunit = nullptr;          // 128 quantisation steps of the pass
+  double* cout = nullptr;           // 128 x 8 certificate outputs
   int max_code = -1;                // largest byte of an int8 store (-1: not measured)
   // unpenalized feature columns (weight 0) of the current problem, for the certificate
   std::vector<int64_t> unpen;
@@ -1345,6 +1351,12 @@ pqr_status batch_alloc(pqr_ctx* ctx, int Kp) {
     TRY(dalloc(ctx, &ctx->cert4, (size_t)4 * g.n_pad * 8));
     TRY(dalloc(ctx, &ctx->out4, 32 * 8));
     TRY(dalloc(ctx, &ctx->gmax4, (size_t)4 * ng * 8));
+    TRY(dalloc(ctx, &ctx->cdig, (size_t)kCertSlices * 128 * g.n_pad));
+    TRY(dalloc(ctx, &ctx->ctq, (size_t)g.n_pad * 4));
+    TRY(dalloc(ctx, &ctx->cgmax, (size_t)128 * cert_group_sets(g) * 8));
+    TRY(dalloc(ctx, &ctx->clamk, 128 * 8));
+    TRY(dalloc(ctx, &ctx->cunit, 128 * 8));
+    TRY(dalloc(ctx, &ctx->cout, 128 * 8 * 8));
   }
   b.cm = ctx->cm_f;
   b.cinv = ctx->cinv_f;
@@ -1429,11 +1441,52 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
     HIPCHK(hipStreamSynchronize(s));
     return PQR_OK;
   };
-  // FP64 certificates of the right-hand sides in `ks`, four at a time: the
-  // projections per k, one shared pass over X for the dual ratios (the dense
-  // part), then the sparse primal per k.  Same arithmetic as pqr_kkt.
+  // P(beta_k) into out[0] + out[1] (the sparse primal, FP64).
+  auto primal_of = [&](int k, double* out) -> pqr_status {
+    const float* bk = b.beta + (size_t)k * g.p_pad;
+    double b0 = 0.0;
+    HIPCHK(hipMemcpyAsync(&b0, b.beta0 + k, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    Ctl c;
+    std::memset(&c, 0, sizeof(c));
+    c.beta0 = b0;
+    HIPCHK(hipMemcpyAsync(ctx->ctl_kkt, &c, sizeof(Ctl), hipMemcpyHostToDevice, s));
+    IterBufs<float> v = bufs<float>(ctx);
+    v.beta = const_cast<float*>(bk);
+    v.ctl = ctx->ctl_kkt;
+    HIPCHK(launch_active_list<float>(g, v, s));
+    HIPCHK(launch_scale(ctx->w_d, lambdas[k], g.p_pad, ctx->clam_d, s));
+    HIPCHK(launch_to_double<float>(bk, g.p_pad, ctx->beta_d, s));
+    CertBufs cb{};
+    cb.y = ctx->y_d;
+    cb.theta_p = ctx->cert4;
+    cb.beta_d = ctx->beta_d;
+    cb.cm = ctx->cm_d;
+    cb.cinv = ctx->cinv_d;
+    cb.clam = ctx->clam_d;
+    cb.partial = ctx->partial64;
+    cb.list = ctx->list;
+    cb.ctl = ctx->ctl_kkt;
+    cb.bpart = ctx->bpart64;
+    cb.out = out;
+    HIPCHK(launch_primal64(g, cb, taus[k], ctx->smax, ctx->min_per, s));
+    HIPCHK(hipStreamSynchronize(s));   // c and b0 leave scope
+    return PQR_OK;
+  };
+  // o = [primal loss, penalty, y^T theta, max ratio, ...]: alpha = min(1, 1 / ratio)
+  auto finish = [&](int k, const double* o) {
+    const double mr = o[3];
+    const double alpha = mr > 1.0 ? (std::isinf(mr) ? 0.0 : 1.0 / mr) : 1.0;
+    ++certs;
+    best_dual[k] = std::max(best_dual[k], alpha * o[2]);
+    primal[k] = o[0] + o[1];
+    rel[k] = (primal[k] - best_dual[k]) / std::max(std::fabs(primal[k]), 1e-300);
+  };
+  // FP64 certificates, four right-hand sides per pass over X: the projections per
+  // k, one shared pass for the dual ratios, then the sparse primal per k.  Same
+  // arithmetic as pqr_kkt.
   std::vector<double> bout(32);
-  auto certify_many = [&](const std::vector<int>& ks) -> pqr_status {
+  auto certify_fp64 = [&](const std::vector<int>& ks) -> pqr_status {
     for (size_t c0 = 0; c0 < ks.size(); c0 += 4) {
       const int kb = (int)std::min<size_t>(4, ks.size() - c0);
       double lam4[4] = {0, 0, 0, 0};
@@ -1448,49 +1501,61 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
       for (int i = 0; i < kb; ++i)
         HIPCHK(launch_reduce_max(ctx->gmax4 + (size_t)i * ng, ng, ctx->bpart64,
                                  ctx->out4 + 8 * i + 3, s));
-      for (int i = 0; i < kb; ++i) {
-        const int k = ks[c0 + i];
-        const float* bk = b.beta + (size_t)k * g.p_pad;
-        double b0 = 0.0;
-        HIPCHK(hipMemcpyAsync(&b0, b.beta0 + k, 8, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        Ctl c;
-        std::memset(&c, 0, sizeof(c));
-        c.beta0 = b0;
-        HIPCHK(hipMemcpyAsync(ctx->ctl_kkt, &c, sizeof(Ctl), hipMemcpyHostToDevice, s));
-        IterBufs<float> v = bufs<float>(ctx);
-        v.beta = const_cast<float*>(bk);
-        v.ctl = ctx->ctl_kkt;
-        HIPCHK(launch_active_list<float>(g, v, s));
-        HIPCHK(launch_scale(ctx->w_d, lambdas[k], g.p_pad, ctx->clam_d, s));
-        HIPCHK(launch_to_double<float>(bk, g.p_pad, ctx->beta_d, s));
-        CertBufs cb{};
-        cb.y = ctx->y_d;
-        cb.theta_p = ctx->cert4 + (size_t)i * g.n_pad;
-        cb.beta_d = ctx->beta_d;
-        cb.cm = ctx->cm_d;
-        cb.cinv = ctx->cinv_d;
-        cb.clam = ctx->clam_d;
-        cb.partial = ctx->partial64;
-        cb.list = ctx->list;
-        cb.ctl = ctx->ctl_kkt;
-        cb.bpart = ctx->bpart64;
-        cb.out = ctx->out4 + 8 * i;
-        HIPCHK(launch_primal64(g, cb, taus[k], ctx->smax, ctx->min_per, s));
-      }
+      for (int i = 0; i < kb; ++i) TRY(primal_of(ks[c0 + i], ctx->out4 + 8 * i));
       HIPCHK(hipMemcpyAsync(bout.data(), ctx->out4, 32 * 8, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      for (int i = 0; i < kb; ++i) {
+      for (int i = 0; i < kb; ++i) finish(ks[c0 + i], bout.data() + 8 * i);
+    }
+    return PQR_OK;
+  };
+  // Exact certificates of the right-hand sides in `ks`: per k the projection
+  // theta' and its quantisation theta_q = unit_k T_k (inside the box, sum exactly
+  // zero), then ONE int8 matrix-core pass over X for the dual ratios of all of
+  // them (x~_j^T theta_q exact in integers), then the sparse primal per k.  A k
+  // whose sum cannot be zeroed inside the box is certified in FP64 instead.
+  std::vector<double> cout_h(8 * 128), lam_h(128), unit_h(128);
+  const int64_t ngs = cert_group_sets(g);
+  auto certify_many = [&](const std::vector<int>& ks) -> pqr_status {
+    std::vector<int> fallback;
+    for (size_t c0 = 0; c0 < ks.size(); c0 += 128) {
+      const int nk = (int)std::min<size_t>(128, ks.size() - c0);
+      const int Kc = (nk + 15) / 16 * 16;
+      for (int i = 0; i < Kc; ++i) { lam_h[i] = 1.0; unit_h[i] = 0.0; }
+      for (int i = 0; i < nk; ++i) {
         const int k = ks[c0 + i];
-        const double* o = bout.data() + 8 * i;
-        const double mr = o[3];
-        const double alpha = mr > 1.0 ? (std::isinf(mr) ? 0.0 : 1.0 / mr) : 1.0;
-        ++certs;
-        best_dual[k] = std::max(best_dual[k], alpha * o[2]);
-        primal[k] = o[0] + o[1];
-        rel[k] = (primal[k] - best_dual[k]) / std::max(std::fabs(primal[k]), 1e-300);
+        // unit = c 2^-27 with c the power of two >= max(tau, 1 - tau) / n >= |theta'_i|
+        int e = 0;
+        (void)std::frexp(std::max(taus[k], 1.0 - taus[k]) / (double)g.n, &e);
+        unit_h[i] = std::ldexp(1.0, e - (7 * kCertSlices - 1));
+        lam_h[i] = lambdas[k];
+        HIPCHK(launch_project<float>(b.theta + (size_t)k * g.n_pad, g.n, g.n_pad, taus[k], ctx->y_d,
+                                     ctx->cert4, ctx->out4, s));
+        HIPCHK(launch_cert_quantize(ctx->cert4, g.n, g.n_pad, taus[k], unit_h[i], ctx->y_d, ctx->ctq,
+                                    ctx->cdig, i, Kc, ctx->cout + 8 * i, s));
+      }
+      HIPCHK(hipMemcpyAsync(ctx->clamk, lam_h.data(), Kc * 8, hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(ctx->cunit, unit_h.data(), Kc * 8, hipMemcpyHostToDevice, s));
+      CertArgs ca{};
+      ca.dig = ctx->cdig;
+      ca.lam = ctx->clamk;
+      ca.unit = ctx->cunit;
+      ca.w = ctx->w_d;
+      ca.cinv = ctx->cinv_d;
+      ca.gmax = ctx->cgmax;
+      ca.K = nk;
+      HIPCHK(launch_cert_pass(g, ca, Kc, s));
+      for (int i = 0; i < nk; ++i)
+        HIPCHK(launch_reduce_max(ctx->cgmax + (size_t)i * ngs, ngs, ctx->bpart64,
+                                 ctx->cout + 8 * i + 3, s));
+      for (int i = 0; i < nk; ++i) TRY(primal_of(ks[c0 + i], ctx->cout + 8 * i));
+      HIPCHK(hipMemcpyAsync(cout_h.data(), ctx->cout, (size_t)nk * 8 * 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      for (int i = 0; i < nk; ++i) {
+        if (cout_h[8 * i + 7] != 0.0) fallback.push_back(ks[c0 + i]);
+        else finish(ks[c0 + i], cout_h.data() + 8 * i);
       }
     }
+    if (!fallback.empty()) TRY(certify_fp64(fallback));
     for (int k : ks)
       if (rel[k] <= ctx->opt.tol_gap && !done[k]) { done[k] = 1; ++ndone; }
     return PQR_OK;

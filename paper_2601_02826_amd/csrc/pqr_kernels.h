@@ -222,6 +222,32 @@ hipError_t launch_batch_iteration(const Geom& g, const BatchBufs& b, int Kp, dou
                                   double sigma, double eta0, int smax, int min_per,
                                   hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_batch_zero(const Geom& g, const BatchBufs& b, int Kp, hipStream_t s);
+
+// Exact-integer certificate of batched right-hand sides.  theta_q,k = unit_k T_k
+// with T_k integer, inside the dual box and summing to exactly zero; its digits
+// (kCertSlices balanced base-128 slices) feed one int8 matrix-core pass over X.
+constexpr int kCertSlices = 4;
+struct CertArgs {
+  const int8_t* dig;    // [kCertSlices][Kc][n_pad] digits of T
+  const double* lam;    // Kc lambda_k (padding: anything finite)
+  const double* unit;   // Kc value of one step of T_k
+  const double* w;      // p_pad penalty weights (> 0 for j < p)
+  const double* cinv;   // p_pad 1 / s_j
+  double* gmax;         // [Kc][ngroups / 4 rounded up] maxima of |x~_j^T theta_q| / (lambda_k w_j)
+  int K;                // right-hand sides in the pass (k >= K: padding)
+};
+// T = trunc(theta' / unit) (toward zero, so inside [(tau-1)/n, tau/n]), its sum
+// made zero by moving the largest (sum > 0) or smallest (sum < 0) entry when that
+// stays in the box; digits into column kc of c.dig (Kc columns); out[2] = y^T theta_q,
+// out[7] = 0 (ok) or 1 (the sum could not be zeroed: certify this k in FP64).
+// tq: n_pad ints of scratch.
+hipError_t launch_cert_quantize(const double* theta_p, int64_t n, int64_t n_pad, double tau,
+                                double unit, const double* y, int* tq, int8_t* dig, int kc,
+                                int Kc, double* out, hipStream_t s);
+// One pass over X for the Kc = 16 m columns of c.dig: c.gmax.
+hipError_t launch_cert_pass(const Geom& g, const CertArgs& c, int Kc, hipStream_t s);
+// Group sets of the certificate pass (the row count of c.gmax per k).
+int64_t cert_group_sets(const Geom& g);
 // largest byte of the int8 store into *out (device int, set to 0 first by the launcher)
 hipError_t launch_max_code(const Geom& g, int* out, hipStream_t s);
 // flags, count and ordered list of the groups holding a nonzero of beta (b.beta);

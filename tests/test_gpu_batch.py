@@ -1,5 +1,7 @@
 """Batched right-hand sides on the int8 matrix cores: every (tau_k, lambda_k) reaches
-its certified gap and agrees with the LP optimum of its own problem."""
+its certified gap and agrees with the LP optimum of its own problem; the certified
+dual (an exactly representable dual point, products exact in integers) never
+exceeds that optimum."""
 import numpy as np
 import pytest
 
@@ -35,6 +37,8 @@ def test_batch_matches_lp_optimum(K, checked):
         assert res[k]["rel_gap"] <= 1e-5, (k, res[k]["rel_gap"])
         assert val * (1 - 1e-12) <= p_gpu <= val * (1 + 1e-5) + 1e-12, (k, p_gpu, val)
         assert res[k]["primal"] == pytest.approx(p_gpu, rel=1e-10)
+        # the certificate's dual point is feasible: its objective cannot pass the optimum
+        assert res[k]["dual"] <= val + 1e-10 * abs(val), (k, res[k]["dual"], val)
     ctx.close()
 
 
