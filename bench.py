@@ -447,6 +447,7 @@ def bench_batched(a):
             r = ctx.solve(y, t, lam, start="zero" if k == 0 else "device", allow_not_converged=True)
             plain_iters += r["iters"]
             plain_conv += r["status"] == 0
+        log(f"  plain path tau={t:g}: {len(ll)} solves, {time.perf_counter() - t0:.1f}s so far")
     plain_s = time.perf_counter() - t0 if not a.skip_reference else None
     Kp = (K + 15) // 16 * 16
     n, p = a.n, a.p
