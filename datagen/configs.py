@@ -10,6 +10,8 @@ Counter layout (every draw is one Philox4x32-10 call, key = (seed, tag)):
     stream 6  Gaussian entry (i, j)    counter (i, j, 6, 0), words 0 and 1
     stream 7  Gaussian-design truth    counter (j, 0, 7, 0), words 0..2
     stream 8  grouped problem i shape  counter (i, 0, 8, 0), words 0..2
+    stream 9  AR(1) innovation (i, j)  counter (i, j, 9, 0), words 0 and 1
+    stream 10 AR(1)-design noise of i  counter (i, 0, 10, 0), words 0 and 1
 
 A genotype entry is the sum of two Bernoulli(MAF_j) draws, x = [w0 < T_j] +
 [w1 < T_j], with the integer threshold T_j = floor(MAF_j * 2^32).  Because the
@@ -91,6 +93,45 @@ def make_gaussian(spec: GaussianSpec):
     beta_star[support + 1] = sign * mag
     y = X @ beta_star[1:] + _t3_noise(spec.seed, spec.tag, np.arange(n, dtype=np.uint64))
     return dict(X=X, y=y, beta_star=beta_star, support=support + 1)
+
+
+def make_ar1(n, p, seed=11, tag=11, rho=0.5, chunk_cols=2048):
+    """The sparse simulation design of Sec. 7.1 (eq. dgp_simulation): X~ ~ N(0, Sigma)
+    with Sigma_ij = rho^|i-j| (an AR(1) recursion over columns with N(0,1)
+    innovations, stream 9), X_1 = Phi(X~_1), X_j = X~_j otherwise, and
+    y = X_6 - X_20 + X_50 - X_100 + X_500 - X_1000 + X_p + 0.7 X_1 eps, eps ~ N(0,1)
+    (stream 10); 1-based column names as in the paper, p >= 1000.  Returns
+    dict(X (n x p float32), y, beta_star(tau) callable, support)."""
+    from scipy.special import ndtr, ndtri
+    if p < 1000:
+        raise ValueError("the design names column 1000: p >= 1000")
+    rows = np.arange(n, dtype=np.uint64)[:, None]
+    X = np.empty((n, p), dtype=np.float32)
+    prev = None
+    c = math.sqrt(1.0 - rho * rho)
+    for j0 in range(0, p, chunk_cols):
+        j1 = min(p, j0 + chunk_cols)
+        w = philox4x32(rows, np.arange(j0, j1, dtype=np.uint64)[None, :], 9, 0, seed, tag)
+        e, _ = _normals_from_words(w[0], w[1])
+        for j in range(j1 - j0):
+            col = e[:, j] if prev is None else rho * prev + c * e[:, j]
+            X[:, j0 + j] = col
+            prev = col
+    X1t = X[:, 0].astype(np.float64)
+    X[:, 0] = ndtr(X1t)
+    we = philox4x32(np.arange(n, dtype=np.uint64), 0, 10, 0, seed, tag)
+    eps, _ = _normals_from_words(we[0], we[1])
+    idx = {6: 1.0, 20: -1.0, 50: 1.0, 100: -1.0, 500: 1.0, 1000: -1.0, p: 1.0}
+    Xd = X.astype(np.float64)
+    y = sum(s * Xd[:, k - 1] for k, s in idx.items()) + 0.7 * Xd[:, 0] * eps
+
+    def beta_star(tau):
+        b = np.zeros(p + 1)
+        for k, s in idx.items():
+            b[k] = s
+        b[1] = 0.7 * ndtri(tau)
+        return b
+    return dict(X=X, y=y, beta_star=beta_star, support=np.array(sorted(idx)))
 
 
 def genotype_maf_thresholds(spec: GenotypeSpec, cols=None):

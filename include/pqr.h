@@ -263,6 +263,20 @@ pqr_status pqr_kkt_columns(pqr_ctx* ctx, const double* y, double tau, double lam
 pqr_status pqr_create_subset(pqr_ctx** out, pqr_ctx* parent, const int64_t* cols,
                              int64_t ncols, const pqr_options* opt);
 
+/* Interleaved column order (the Discussion's block-permutation direction: a
+ * column order that lowers Lambda_max(X_g^T X_g) of every block allows smaller
+ * eta_g, i.e. longer beta steps in eq. beta_update).  cols (host, p int64)
+ * receives the feature columns 0..p-1 ordered by (j mod G, j).  A context made
+ * with pqr_create_subset(parent, cols, p, opt) and opt->G = G then has block b
+ * (a contiguous run of its columns) holding residue class b up to the 16-column
+ * alignment of the block bounds, so columns j and j + 1 of the parent sit in
+ * different blocks; where correlation decays with column distance (an AR(1)
+ * design, linkage along a chromosome) the blocks' Gram matrices lose their
+ * off-diagonal mass.  The subset context's per-column arrays (weights, beta,
+ * scores) follow the new order: element 1 + q is parent column cols[q].
+ * Host only (no device work).  Errors: p < 1, G < 1, G > p or cols NULL. */
+pqr_status pqr_interleaved_order(int64_t p, int G, int64_t* cols);
+
 /* ---- learned warm start: the per-feature scoring network ------------------
  * Network 4 -> 64 -> 64 -> 2 with SiLU activations; 4610 FP32 parameters in the
  * order W1[64][4], b1[64], W2[64][64], b2[64], W3[2][64], b3[2], used as BF16

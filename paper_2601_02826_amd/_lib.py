@@ -50,7 +50,7 @@ SYMBOLS = ["pqr_default_options", "pqr_create", "pqr_solve", "pqr_kkt", "pqr_lam
            "pqr_blocks", "pqr_iterate", "pqr_solve_batch", "pqr_kkt_columns", "pqr_create_subset",
            "pqr_mlp_param_count", "pqr_features", "pqr_mlp_forward", "pqr_mlp_workspace_bytes",
            "pqr_mlp_grad", "pqr_mlp_adam", "pqr_solve_learned", "pqr_solve_grouped", "pqr_solve_lla",
-           "pqr_destroy", "pqr_last_error", "pqr_status_string"]
+           "pqr_interleaved_order", "pqr_destroy", "pqr_last_error", "pqr_status_string"]
 
 
 class pqr_learned_report(ctypes.Structure):
@@ -97,6 +97,8 @@ def load():
     lib.pqr_create_subset.argtypes = [ctypes.POINTER(vp), vp, ctypes.POINTER(i64), i64,
                                       ctypes.POINTER(pqr_options)]
     lib.pqr_create_subset.restype = ci
+    lib.pqr_interleaved_order.argtypes = [i64, ci, ctypes.POINTER(i64)]
+    lib.pqr_interleaved_order.restype = ci
     lib.pqr_mlp_param_count.argtypes = []
     lib.pqr_mlp_param_count.restype = i64
     lib.pqr_features.argtypes = [vp, _c_dp, dbl, dbl, _c_dp, _c_fp, _c_dp]
@@ -307,6 +309,14 @@ class Context:
         sub._lib, sub._h, sub.n, sub.p, sub._keep, sub.options = self._lib, h, self.n, len(cols), self, o
         return sub
 
+    def interleaved(self, G=None, **options):
+        """A context over this one's columns in pqr_interleaved_order for G blocks,
+        wrapped so that every per-column array is in this context's order."""
+        options.pop("G", None)
+        G = int(G if G is not None else (self.options.G or 48))
+        cols = interleaved_order(self.p, G)
+        return Interleaved(self.subset(cols, G=G, **options), cols)
+
     def features(self, y, tau, lam, feats_ptr, weights=None):
         """pqr_features into a device buffer of p x 4 floats; returns lambda_max."""
         lm = np.zeros(1)
@@ -393,6 +403,82 @@ class Context:
                                           _dptr(_f64(eta)), int(iters), _dptr(b), _dptr(zz),
                                           _dptr(tt)))
         return b, zz, tt
+
+
+def interleaved_order(p, G):
+    """pqr_interleaved_order: the feature columns 0..p-1 ordered by (j mod G, j)."""
+    cols = np.zeros(int(p), dtype=np.int64)
+    st = load().pqr_interleaved_order(int(p), int(G), cols.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if st != PQR_OK:
+        raise PQRError(st, "pqr_interleaved_order: need 1 <= G <= p")
+    return cols
+
+
+class Interleaved:
+    """A Context over the columns of another in interleaved order (`ctx`, element
+    1 + q is source column cols[q]) with the source order at its surface: weights and
+    coefficients are permuted on the way in and out; nothing else changes."""
+
+    def __init__(self, ctx, cols):
+        self.ctx, self.cols = ctx, np.asarray(cols, dtype=np.int64)
+        self.n, self.p = ctx.n, ctx.p
+
+    def _in(self, a):   # source order (p+1, intercept first) -> context order
+        if a is None:
+            return None
+        a = np.asarray(a, dtype=np.float64)
+        return np.concatenate([a[:1], a[1 + self.cols]])
+
+    def _out(self, a):  # context order -> source order
+        o = np.empty_like(a)
+        o[0] = a[0]
+        o[1 + self.cols] = a[1:]
+        return o
+
+    def _res(self, r):
+        for k in ("beta", "beta_std", "weights"):
+            if k in r and r[k] is not None and len(r[k]) == self.p + 1:
+                r[k] = self._out(r[k])
+        return r
+
+    def solve(self, y, tau, lam, weights=None, start="zero", warm=None, allow_not_converged=False):
+        if warm is not None:
+            warm = {k: (self._in(v) if k in ("beta", "beta_std") else v) for k, v in warm.items()}
+        return self._res(self.ctx.solve(y, tau, lam, weights=self._in(weights), start=start,
+                                        warm=warm, allow_not_converged=allow_not_converged))
+
+    def solve_batch(self, y, taus, lams, weights=None, allow_not_converged=False):
+        return [self._res(r) for r in self.ctx.solve_batch(y, taus, lams, weights=self._in(weights),
+                                                           allow_not_converged=allow_not_converged)]
+
+    def kkt(self, y, tau, lam, beta_std, theta, weights=None):
+        return self.ctx.kkt(y, tau, lam, self._in(beta_std), theta, weights=self._in(weights))
+
+    def lambda_max(self, y, tau, weights=None, score=False):
+        r = self.ctx.lambda_max(y, tau, weights=self._in(weights), score=score)
+        if not score:
+            return r
+        lm, sc = r
+        o = np.empty_like(sc)
+        o[self.cols] = sc
+        return lm, o
+
+    def blocks(self):
+        """(G, bounds, Lambda) of the context; bounds are positions in `cols`."""
+        return self.ctx.blocks()
+
+    def block_columns(self):
+        """The source feature columns (0-based) of every block, in block order."""
+        G, bounds, _ = self.ctx.blocks()
+        return [self.cols[bounds[b]:bounds[b + 1]] for b in range(G)]
+
+    def iterate(self, y, tau, lam, mu, eta, iters, beta_std, z, theta, weights=None):
+        b, zz, tt = self.ctx.iterate(y, tau, lam, mu, eta, iters, self._in(beta_std), z, theta,
+                                     weights=self._in(weights))
+        return self._out(b), zz, tt
+
+    def close(self):
+        self.ctx.close()
 
 
 # ---- the scoring network: free functions over device buffers (torch tensors) ----

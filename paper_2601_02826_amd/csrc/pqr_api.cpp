@@ -1734,6 +1734,14 @@ extern "C" pqr_status pqr_create_subset(pqr_ctx** out, pqr_ctx* parent, const in
   return create_subset_impl(ctx, parent, cols, ncols);
 }
 
+extern "C" pqr_status pqr_interleaved_order(int64_t p, int G, int64_t* cols) {
+  if (p < 1 || G < 1 || G > p || !cols) return PQR_ERR_INVALID_ARG;
+  int64_t q = 0;
+  for (int r = 0; r < G; ++r)
+    for (int64_t j = r; j < p; j += G) cols[q++] = j;
+  return PQR_OK;
+}
+
 extern "C" pqr_status pqr_features(pqr_ctx* ctx, const double* y, double tau, double lambda,
                                    const double* weights, float* feats, double* lambda_max) {
   if (!ctx) return PQR_ERR_INVALID_ARG;
