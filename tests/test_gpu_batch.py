@@ -39,6 +39,10 @@ def test_batch_matches_lp_optimum(K, checked):
         assert res[k]["primal"] == pytest.approx(p_gpu, rel=1e-10)
         # the certificate's dual point is feasible: its objective cannot pass the optimum
         assert res[k]["dual"] <= val + 1e-10 * abs(val), (k, res[k]["dual"], val)
+        # and it loses no more than its quantisation (2^-27 of the box per entry) against
+        # the oracle's FP64 certificate of the returned (certified) iterate
+        ref = pqr.dual_certificate(X1, y, taus[k], lam_vec, res[k]["beta_std"], res[k]["theta"])
+        assert res[k]["dual"] >= ref["dual"] - 1e-6 * abs(ref["dual"]), (k, res[k]["dual"], ref["dual"])
     ctx.close()
 
 
