@@ -16,7 +16,8 @@ Conventions
 Pins (see tests/test_oracle_*.py): prox maps against brute-force 1-D
 minimisation; lambda_max and the intercept-only fit against the sample-quantile
 closed form; the full solve against an exact rational simplex, vertex
-enumeration and HiGHS; the certificate by weak duality; the step by the
+enumeration and HiGHS; the certificates (FP64 and on the quantised dual point) by
+weak duality, exact feasibility and agreement with each other; the step by the
 non-increase of the H-norm successive difference.
 """
 import math
@@ -280,6 +281,50 @@ def dual_certificate(X1, y, tau, lam, beta, theta):
     gap = primal - dual
     return dict(primal=primal, dual=dual, gap=gap, rel_gap=gap / max(abs(primal), 1e-300),
                 theta_feasible=tf, alpha=alpha)
+
+
+def quantized_dual_certificate(X1, y, tau, lam, beta, theta, slices=4):
+    """Weak-duality certificate on an exactly representable dual point (Prop. 1 holds
+    for any point of the dual feasible set; the batched form's reading).  theta' is
+    the shift-and-clip projection of dual_certificate (positive weights only).  With
+    unit = c 2^-(7 slices - 1), c the power of two >= max(tau, 1 - tau)/n, the point
+    is theta_q = unit T with T = trunc(theta'/unit) (toward zero, so inside the box).
+    The integer sum of T is moved onto its largest entry (sum > 0) or its smallest
+    (sum < 0), the first index on ties, so that sum theta_q = 0 exactly; if that
+    entry would leave the box the function returns None.  Then alpha = min(1, min_j
+    lam_j / |x_j^T theta_q|) and the dual value is alpha y^T theta_q."""
+    n = X1.shape[0]
+    lam = np.asarray(lam, dtype=np.float64)
+    if np.any(lam[1:] <= 0):
+        raise ValueError("positive feature weights only")
+    lo, hi = (tau - 1.0) / n, tau / n
+    tp = project_box_sum(theta, lo, hi)
+    _, e = math.frexp(max(tau, 1.0 - tau) / n)
+    unit = math.ldexp(1.0, e - (7 * slices - 1))
+    t_lo, t_hi = math.ceil(lo / unit), math.floor(hi / unit)
+    T = np.clip(np.trunc(tp / unit), t_lo, t_hi).astype(np.int64)
+    s = int(T.sum())
+    if s > 0:
+        i = int(np.argmax(T))
+        if T[i] - s < t_lo:
+            return None
+        T[i] -= s
+    elif s < 0:
+        i = int(np.argmin(T))
+        if T[i] - s > t_hi:
+            return None
+        T[i] -= s
+    tq = T.astype(np.float64) * unit
+    v = X1[:, 1:].T @ tq
+    alpha = 1.0
+    for vj, l in zip(np.abs(v), lam[1:]):
+        if vj > l:
+            alpha = min(alpha, l / vj)
+    primal = objective(X1, y, beta, tau, lam)
+    dual = alpha * _sum(y * tq)
+    gap = primal - dual
+    return dict(primal=primal, dual=dual, gap=gap, rel_gap=gap / max(abs(primal), 1e-300),
+                T=T, unit=unit, alpha=alpha, t_lo=t_lo, t_hi=t_hi)
 
 
 def kkt_violation(X1, y, tau, lam, beta, theta, zero_tol=0.0):

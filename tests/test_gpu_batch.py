@@ -43,6 +43,12 @@ def test_batch_matches_lp_optimum(K, checked):
         # the oracle's FP64 certificate of the returned (certified) iterate
         ref = pqr.dual_certificate(X1, y, taus[k], lam_vec, res[k]["beta_std"], res[k]["theta"])
         assert res[k]["dual"] >= ref["dual"] - 1e-6 * abs(ref["dual"]), (k, res[k]["dual"], ref["dual"])
+        # the oracle of the same reading (quantised point, exact zero sum) agrees to
+        # rounding: the device's dual is the best of its rounds, the last one at least
+        qref = pqr.quantized_dual_certificate(X1, y, taus[k], lam_vec, res[k]["beta_std"],
+                                              res[k]["theta"])
+        assert qref is not None
+        assert res[k]["dual"] >= qref["dual"] - 1e-9 * abs(qref["dual"]), (k, res[k]["dual"], qref["dual"])
     ctx.close()
 
 

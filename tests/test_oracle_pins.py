@@ -259,6 +259,40 @@ def test_certificate_weak_duality_with_unpenalized_columns(standardized):
     assert val * (1 - 1e-12) <= res["primal"] <= val * (1 + 1e-8) + 1e-12
 
 
+@pytest.mark.parametrize("tau", [0.1, 0.5, 0.93])
+def test_quantized_certificate_exact_feasibility_and_agreement(tau):
+    """The exactly representable dual point theta_q = unit T: its integer sum is zero,
+    every entry lies in the box (checked in exact rationals against the FP64 bounds),
+    its dual value bounds the LP optimum from below, and at a near-optimal iterate it
+    is within the quantisation (2^-27 of the box per entry) of the FP64 certificate."""
+    n, p = 60, 15
+    X1, y = _tiny(13, n, p)
+    lam = np.full(p + 1, 0.2 * pqr.lambda_max(X1, y, tau))
+    lam[0] = 0.0
+    val, _ = lp.highs(X1, y, tau, lam)
+    lo, hi = Fraction((tau - 1.0) / n), Fraction(tau / n)
+    rng = np.random.default_rng(3)
+    for _ in range(30):
+        beta = rng.standard_normal(p + 1) * 0.3
+        theta = rng.standard_normal(n) * 0.02
+        c = pqr.quantized_dual_certificate(X1, y, tau, lam, beta, theta)
+        assert c is not None
+        T, unit = c["T"], Fraction(c["unit"])
+        assert int(T.sum()) == 0
+        assert all(lo <= int(t) * unit <= hi for t in T)
+        assert c["dual"] <= val + 1e-12
+        assert 0.0 < c["alpha"] <= 1.0
+    blocks = pqr.partition(p, 3)
+    mu = pqr.default_mu(y, 3)
+    eta = pqr.step_sizes(X1, blocks, mu)
+    res = pqr.fsqrppa(X1, y, tau, lam, blocks, mu, eta, tol_gap=1e-8, max_iter=400_000)
+    cf = pqr.dual_certificate(X1, y, tau, lam, res["beta"], res["theta"])
+    cq = pqr.quantized_dual_certificate(X1, y, tau, lam, res["beta"], res["theta"])
+    assert cf["rel_gap"] <= 1e-8
+    assert abs(cq["dual"] - cf["dual"]) <= 1e-6 * abs(cf["dual"])
+    assert val * (1 - 1e-6) <= cq["dual"] <= val + 1e-12
+
+
 def test_h_norm_successive_difference_non_increasing():
     X1, y = _tiny(4, 70, 40)
     tau, G = 0.5, 4
