@@ -110,7 +110,7 @@ typedef struct {
   double* theta;
   int64_t iters;        /* FS-QRPPA iterations run                              */
   int64_t x_passes;     /* full reads of X (iterations + certificates + setup of this call) */
-  int64_t certs;        /* FP64 certificates evaluated                         */
+  int64_t certs;        /* duality-gap certificates evaluated                   */
   int64_t nnz;          /* nonzero coefficients (intercept excluded)            */
   double primal;        /* P(beta) in FP64                                      */
   double dual;          /* dual objective of the feasible point built from theta */
@@ -214,10 +214,15 @@ pqr_status pqr_solve_lla(pqr_ctx* ctx, const double* y, double tau, double lambd
 /* K problems that share X, y and the weights, with their own (tau_k, lambda_k),
  * solved together (Algorithm 1 for every k, iterated in lockstep).  The back-
  * products X~^T Theta of all k run on the int8 matrix cores over digit slices of
- * theta (exact integer arithmetic); every k is stopped by its own FP64 duality-gap
- * certificate (pqr_kkt's).  Needs an int8 store with codes 0..127, rows_per_lane
- * 16, FP32 iterates and positive weights (PQR_ERR_UNSUPPORTED otherwise);
- * 1 <= K <= 128.
+ * theta (exact integer arithmetic); every k is stopped by its own duality-gap
+ * certificate (Prop. 1) on an exactly representable dual point: the projected theta'
+ * truncated toward zero to multiples of unit_k = c 2^-27 (c the power of two
+ * >= max(tau_k, 1 - tau_k)/n), its integer sum moved onto the largest or smallest
+ * entry so that it sums to zero exactly, the dual ratios x~_j^T theta_q exact in
+ * integers from one int8 matrix-core pass for all due k (pqr_kkt's FP64 pass for a k
+ * whose sum cannot be moved inside the box).  Needs an int8 store with codes 0..127,
+ * rows_per_lane 16, FP32 iterates and positive weights (PQR_ERR_UNSUPPORTED
+ * otherwise); 1 <= K <= 128.
  *  y, weights  as in pqr_solve;  taus, lambdas  host, K doubles each
  *  outs        host array of K pqr_result (output arrays optional, as in pqr_solve);
  *              beta/z/theta are the final iterate, rel_gap its certified gap
