@@ -101,11 +101,12 @@ template <int N, class F> __device__ __forceinline__ void static_for(F&& f) {
 }
 
 // SPT = 64-row steps per digit tile (one barrier per tile); WPB = wavefronts per
-// block (all of them share each staged digit tile); NS = A fragment sets in flight.
+// block (all of them share each staged digit tile); NS = A fragment sets in flight
+// (A from registers); SA = A staged in LDS once per group set and tile.
 // S = digit slices; CERT selects the certificate epilogue (per (group set, k)
 // maxima of |x~_j^T theta_q| / (lambda_k w_j)) over the iteration's (eq.
 // beta_update and the column masks).  The column groups of block bi over all rows.
-template <int TW, int GW, int DL, int SPT, int WPB, int NS, int S, bool CERT>
+template <int TW, int GW, int DL, int SPT, int WPB, int NS, int S, bool CERT, bool SA>
 __device__ __forceinline__ void bgemm_pass(const Geom& g, const BatchBufs& b, const CertArgs& ca,
                                            int Kp, int wps, int64_t bi, uint8_t* dtile) {
   constexpr int kDRow = drow_bytes<SPT>();
@@ -200,45 +201,98 @@ __device__ __forceinline__ void bgemm_pass(const Geom& g, const BatchBufs& b, co
         for (int s = 0; s < S; ++s)
           acc[q][r][s] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[q], bf[r][s], acc[q][r][s], 0, 0, 0);
   };
-  // NS A fragment sets in rotation: step t uses set t % NS, and right after its
-  // MFMAs issue the set is reloaded for step t + NS, so NS - 1 steps' loads are in
-  // flight while these MFMAs run.  The next digit tile is loaded at the top of a
-  // tile and stored to the other LDS buffer at its end; one barrier per tile.
-  // Scheduling barriers keep this order; loads past the end re-read the last step
-  // or tile (in bounds).  The loop body is L = lcm(NS, SPT) steps, unrolled so that
-  // the set and the step within the tile are compile-time constants.
-  constexpr int L = NS * SPT / gcd_c(NS, SPT);
-  v4i aS[NS][GW], bf[TW][S];
+  v4i bf[TW][S];
   v4u dr[DL];
-  load_d(0, dr);
-  store_d(0, dr);
-  __syncthreads();
-  static_for<NS>([&](auto I) {   // each set strictly older than the next on entry
-    load_a(I.value < nsteps ? I.value : nsteps - 1, aS[I.value]);
-    __builtin_amdgcn_sched_barrier(0);
-  });
-  for (int64_t t0 = 0; t0 < nsteps; t0 += L) {
-    static_for<L>([&](auto I) {
-      constexpr int set = I.value % NS, h = I.value % SPT;
-      const int64_t t = t0 + I.value;
-      const int64_t u = t / SPT;   // digit tile
-      const int buf = (int)(u & 1);
-      if constexpr (h == 0) {
-        load_d(u + 1 < nsup ? u + 1 : nsup - 1, dr);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-      if (kStepsDivide<L>() || t < nsteps) {   // wave-uniform
-        read_b(buf, h, bf);
-        mma(aS[set], bf);
-      }
+  if constexpr (!SA) {
+    // NS A fragment sets in rotation: step t uses set t % NS, and right after its
+    // MFMAs issue the set is reloaded for step t + NS, so NS - 1 steps' loads are in
+    // flight while these MFMAs run.  The next digit tile is loaded at the top of a
+    // tile and stored to the other LDS buffer at its end; one barrier per tile.
+    // Scheduling barriers keep this order; loads past the end re-read the last step
+    // or tile (in bounds).  The loop body is L = lcm(NS, SPT) steps, unrolled so that
+    // the set and the step within the tile are compile-time constants.
+    constexpr int L = NS * SPT / gcd_c(NS, SPT);
+    v4i aS[NS][GW];
+    load_d(0, dr);
+    store_d(0, dr);
+    __syncthreads();
+    static_for<NS>([&](auto I) {   // each set strictly older than the next on entry
+      load_a(I.value < nsteps ? I.value : nsteps - 1, aS[I.value]);
       __builtin_amdgcn_sched_barrier(0);
-      load_a(t + NS < nsteps ? t + NS : nsteps - 1, aS[set]);
-      __builtin_amdgcn_sched_barrier(0);
-      if constexpr (h == SPT - 1) {
-        store_d(buf ^ 1, dr);
-        __syncthreads();
-      }
     });
+    for (int64_t t0 = 0; t0 < nsteps; t0 += L) {
+      static_for<L>([&](auto I) {
+        constexpr int set = I.value % NS, h = I.value % SPT;
+        const int64_t t = t0 + I.value;
+        const int64_t u = t / SPT;   // digit tile
+        const int buf = (int)(u & 1);
+        if constexpr (h == 0) {
+          load_d(u + 1 < nsup ? u + 1 : nsup - 1, dr);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        if (kStepsDivide<L>() || t < nsteps) {   // wave-uniform
+          read_b(buf, h, bf);
+          mma(aS[set], bf);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        load_a(t + NS < nsteps ? t + NS : nsteps - 1, aS[set]);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (h == SPT - 1) {
+          store_d(buf ^ 1, dr);
+          __syncthreads();
+        }
+      });
+    }
+  } else {
+    // Shared A: the wps wavefronts of a group set need the same A fragments, so
+    // each tile's GW x SPT fragments of the set are staged once in LDS (behind the
+    // digit tiles, double-buffered alongside them) by direct buffer-to-LDS loads
+    // (lane l lands at 16 l: the fragment layout), split among the set's wavefronts.
+    // Tile u + 1's fragments and digits are loaded at the top of tile u; the
+    // barrier at its end (a workgroup fence: every load of the block has landed)
+    // makes them visible to the whole block.
+    constexpr int NGS = WPB;                 // upper bound of group sets per block
+    constexpr int NF = GW * SPT;             // fragments per set and tile
+    const int gsl = wv / wps, wi = wv % wps;
+    const int ngs_blk = WPB / wps;
+    uint8_t* abase = dtile + (size_t)2 * drows * kDRow;
+    auto a_slot = [&](int bufA, int f) {
+      return abase + ((size_t)(bufA * ngs_blk + gsl) * NF + f) * 1024;
+    };
+    auto issue_a = [&](int64_t u, int bufA) {
+      for (int f = wi; f < NF; f += wps) {   // wave-uniform
+        const int h = f / GW, q = f % GW;
+        const int64_t t = u * SPT + h;
+        const int so = (int)((t >> 4) * cstride + (t & 15) * 64);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            arsrc, (__attribute__((address_space(3))) void*)a_slot(bufA, f), 16, (int)aoff[q],
+            so, 0, 0);
+      }
+    };
+    (void)NGS;
+    issue_a(0, 0);
+    load_d(0, dr);
+    store_d(0, dr);
+    __syncthreads();
+    for (int64_t u = 0; u < nsup; ++u) {
+      const int buf = (int)(u & 1);
+      const int64_t un = u + 1 < nsup ? u + 1 : nsup - 1;
+      issue_a(un, buf ^ 1);
+      load_d(un, dr);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int h = 0; h < SPT; ++h) {
+        v4i af[GW];
+#pragma unroll
+        for (int q = 0; q < GW; ++q)
+          af[q] = *reinterpret_cast<const v4i*>(a_slot(buf, h * GW + q) + lane * 16);
+        read_b(buf, h, bf);
+        mma(af, bf);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      store_d(buf ^ 1, dr);
+      __syncthreads();
+    }
   }
   if (!wave_live) return;
   if constexpr (CERT) {
@@ -318,11 +372,12 @@ __device__ __forceinline__ void bgemm_pass(const Geom& g, const BatchBufs& b, co
   }
 }
 
-template <int TW, int GW, int DL, int SPT, int WPB, int NS, int S, bool CERT>
+template <int TW, int GW, int DL, int SPT, int WPB, int NS, int S, bool CERT, bool SA>
 __global__ __launch_bounds__(64 * WPB, 2) void k_bgemm(Geom g, BatchBufs b, CertArgs ca, int Kp,
                                                        int wps) {
-  extern __shared__ __attribute__((aligned(16))) uint8_t dtile[];   // 2 x S*Kp x 64 SPT (+16)
-  bgemm_pass<TW, GW, DL, SPT, WPB, NS, S, CERT>(g, b, ca, Kp, wps, blockIdx.x, dtile);
+  // 2 x S*Kp x (64 SPT + 16) digit bytes, then (SA) 2 x (WPB / wps) x GW SPT KB of A
+  extern __shared__ __attribute__((aligned(16))) uint8_t dtile[];
+  bgemm_pass<TW, GW, DL, SPT, WPB, NS, S, CERT, SA>(g, b, ca, Kp, wps, blockIdx.x, dtile);
 }
 
 // ---------------------------------------------------------------------------
@@ -676,13 +731,14 @@ __global__ void k_bfinal(BatchBufs b, int nblk, int Kp) {
 
 // One k_bgemm launch: groups per block = (WPB / wps) GW, two digit tiles of LDS.
 // The block's threads stage every digit row of a tile: 64 WPB DL >= S Kp * 4 SPT.
-template <int TW, int GW, int DL, int SPT, int WPB, int NS, int S, bool CERT>
+template <int TW, int GW, int DL, int SPT, int WPB, int NS, int S, bool CERT, bool SA = false>
 static hipError_t launch_bgemm(const Geom& g, const BatchBufs& b, const CertArgs& ca, int Kp,
                                int wps, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   if (64 * WPB * DL < S * Kp * 4 * SPT || WPB % wps || Kp > 16 * TW * wps)
     return hipErrorInvalidValue;
-  auto kern = k_bgemm<TW, GW, DL, SPT, WPB, NS, S, CERT>;
-  const size_t lds = (size_t)2 * S * Kp * drow_bytes<SPT>();
+  auto kern = k_bgemm<TW, GW, DL, SPT, WPB, NS, S, CERT, SA>;
+  const size_t lds = (size_t)2 * S * Kp * drow_bytes<SPT>() +
+                     (SA ? (size_t)2 * (WPB / wps) * GW * SPT * 1024 : 0);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   const int64_t per_block = (int64_t)(WPB / wps) * GW;
   const dim3 grid((unsigned)((g.ngroups() + per_block - 1) / per_block));
@@ -790,7 +846,8 @@ int64_t cert_group_sets(const Geom& g) { return (g.ngroups() + 3) / 4; }
 
 // GW = 4 groups per wavefront (the group sets of c.gmax); 8-wavefront blocks;
 // 4 slices hold 32 accumulator registers more than an iteration's 3, so the
-// digit tiles are shorter (at most 4 staging loads per thread, no spills).
+// digit tiles are shorter (at most 5 staging loads per thread, no spills); shared
+// A from 3 tiles on, as in the iteration.
 hipError_t launch_cert_pass(const Geom& g, const CertArgs& c, int Kc, hipStream_t s) {
   if (g.fmt != I8 || g.rpl != 16 || Kc % 16 || Kc < 16 || Kc > 128 || c.K > Kc)
     return hipErrorInvalidValue;
@@ -799,12 +856,12 @@ hipError_t launch_cert_pass(const Geom& g, const CertArgs& c, int Kc, hipStream_
   switch (Kc / 16) {   // DL = ceil(16 SPT Kc / (64 WPB))
     case 1: return launch_bgemm<1, 4, 1, 2, 8, 2, S, true>(g, b, c, Kc, 1, s, nullptr, nullptr);
     case 2: return launch_bgemm<2, 4, 2, 2, 8, 2, S, true>(g, b, c, Kc, 1, s, nullptr, nullptr);
-    case 3: return launch_bgemm<2, 4, 4, 2, 8, 2, S, true>(g, b, c, Kc, 2, s, nullptr, nullptr);
-    case 4: return launch_bgemm<2, 4, 4, 2, 8, 2, S, true>(g, b, c, Kc, 2, s, nullptr, nullptr);
-    case 5: return launch_bgemm<2, 4, 5, 2, 8, 2, S, true>(g, b, c, Kc, 4, s, nullptr, nullptr);
-    case 6: return launch_bgemm<2, 4, 4, 1, 8, 2, S, true>(g, b, c, Kc, 4, s, nullptr, nullptr);
-    case 7: return launch_bgemm<2, 4, 4, 1, 8, 2, S, true>(g, b, c, Kc, 4, s, nullptr, nullptr);
-    case 8: return launch_bgemm<2, 4, 4, 1, 8, 2, S, true>(g, b, c, Kc, 4, s, nullptr, nullptr);
+    case 3: return launch_bgemm<2, 4, 4, 2, 8, 2, S, true, true>(g, b, c, Kc, 2, s, nullptr, nullptr);
+    case 4: return launch_bgemm<2, 4, 4, 2, 8, 2, S, true, true>(g, b, c, Kc, 2, s, nullptr, nullptr);
+    case 5: return launch_bgemm<2, 4, 5, 2, 8, 2, S, true, true>(g, b, c, Kc, 4, s, nullptr, nullptr);
+    case 6: return launch_bgemm<2, 4, 4, 1, 8, 2, S, true, true>(g, b, c, Kc, 4, s, nullptr, nullptr);
+    case 7: return launch_bgemm<2, 4, 4, 1, 8, 2, S, true, true>(g, b, c, Kc, 4, s, nullptr, nullptr);
+    case 8: return launch_bgemm<2, 4, 4, 1, 8, 2, S, true, true>(g, b, c, Kc, 4, s, nullptr, nullptr);
   }
   return hipErrorInvalidValue;
 }
@@ -821,19 +878,19 @@ hipError_t launch_batch_iteration(const Geom& g, const BatchBufs& b, int Kp, dou
   // One or two tiles per wavefront, GW = 4 groups (GW * TW * S * 4 <= 96 accumulators);
   // wps = wavefronts sharing a set of groups (1, 2 or 4).  Blocks of 8 wavefronts:
   // at about 200 VGPRs one block fills a CU, so two digit tiles of up to 128 KB of
-  // LDS cost no occupancy, and a staged tile serves 8 GW / wps groups.  Digit tiles
-  // of 256 rows for 3 to 5 tiles, else 128 rows (faster for 1 or 2 tiles; LDS
-  // for 6 to 8).
+  // LDS cost no occupancy, and a staged tile serves 8 GW / wps groups.  128-row
+  // digit tiles; with 3 to 8 tiles (wps >= 2) the set's A fragments are staged
+  // once in LDS too (shared A) instead of being loaded by each of its wavefronts.
   hipError_t e = hipSuccess;
   switch (nrt) {   // DL = ceil(12 SPT Kp / (64 WPB)) digit loads per thread and tile
     case 1: e = launch_bgemm<1, 4, 1, 2, 8, 2, kBS, false>(g, b, CertArgs{}, Kp, 1, s, ev0, ev1); break;
     case 2: e = launch_bgemm<2, 4, 2, 2, 8, 2, kBS, false>(g, b, CertArgs{}, Kp, 1, s, ev0, ev1); break;
-    case 3: e = launch_bgemm<2, 4, 6, 4, 8, 2, kBS, false>(g, b, CertArgs{}, Kp, 2, s, ev0, ev1); break;
-    case 4: e = launch_bgemm<2, 4, 6, 4, 8, 2, kBS, false>(g, b, CertArgs{}, Kp, 2, s, ev0, ev1); break;
-    case 5: e = launch_bgemm<2, 4, 8, 4, 8, 2, kBS, false>(g, b, CertArgs{}, Kp, 4, s, ev0, ev1); break;
-    case 6: e = launch_bgemm<2, 4, 6, 2, 8, 2, kBS, false>(g, b, CertArgs{}, Kp, 4, s, ev0, ev1); break;
-    case 7: e = launch_bgemm<2, 4, 6, 2, 8, 2, kBS, false>(g, b, CertArgs{}, Kp, 4, s, ev0, ev1); break;
-    case 8: e = launch_bgemm<2, 4, 6, 2, 8, 2, kBS, false>(g, b, CertArgs{}, Kp, 4, s, ev0, ev1); break;
+    case 3: e = launch_bgemm<2, 4, 3, 2, 8, 2, kBS, false, true>(g, b, CertArgs{}, Kp, 2, s, ev0, ev1); break;
+    case 4: e = launch_bgemm<2, 4, 3, 2, 8, 2, kBS, false, true>(g, b, CertArgs{}, Kp, 2, s, ev0, ev1); break;
+    case 5: e = launch_bgemm<2, 4, 4, 2, 8, 2, kBS, false, true>(g, b, CertArgs{}, Kp, 4, s, ev0, ev1); break;
+    case 6: e = launch_bgemm<2, 4, 6, 2, 8, 2, kBS, false, true>(g, b, CertArgs{}, Kp, 4, s, ev0, ev1); break;
+    case 7: e = launch_bgemm<2, 4, 6, 2, 8, 2, kBS, false, true>(g, b, CertArgs{}, Kp, 4, s, ev0, ev1); break;
+    case 8: e = launch_bgemm<2, 4, 6, 2, 8, 2, kBS, false, true>(g, b, CertArgs{}, Kp, 4, s, ev0, ev1); break;
   }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_bcount, dim3(kCompactBlocks), dim3(1024), 0, s, g.ngroups(), b, nrt);
