@@ -121,17 +121,19 @@ def make_ar1(n, p, seed=11, tag=11, rho=0.5, chunk_cols=2048):
     X[:, 0] = ndtr(X1t)
     we = philox4x32(np.arange(n, dtype=np.uint64), 0, 10, 0, seed, tag)
     eps, _ = _normals_from_words(we[0], we[1])
-    idx = {6: 1.0, 20: -1.0, 50: 1.0, 100: -1.0, 500: 1.0, 1000: -1.0, p: 1.0}
+    # the named terms as written; at p = 1000, X_1000 and X_p are one column and cancel
+    terms = [(6, 1.0), (20, -1.0), (50, 1.0), (100, -1.0), (500, 1.0), (1000, -1.0), (p, 1.0)]
+    lin = np.zeros(p + 1)
+    for k, s in terms:
+        lin[k] += s
     Xd = X.astype(np.float64)
-    y = sum(s * Xd[:, k - 1] for k, s in idx.items()) + 0.7 * Xd[:, 0] * eps
+    y = Xd @ lin[1:] + 0.7 * Xd[:, 0] * eps
 
     def beta_star(tau):
-        b = np.zeros(p + 1)
-        for k, s in idx.items():
-            b[k] = s
+        b = lin.copy()
         b[1] = 0.7 * ndtri(tau)
         return b
-    return dict(X=X, y=y, beta_star=beta_star, support=np.array(sorted(idx)))
+    return dict(X=X, y=y, beta_star=beta_star, support=np.nonzero(lin)[0])
 
 
 def genotype_maf_thresholds(spec: GenotypeSpec, cols=None):
