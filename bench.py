@@ -326,7 +326,7 @@ def bench_path_batched(a):
     t0 = time.perf_counter()
     for k in range(a.steps):
         res = ctx.solve_batch(y, taus, lams, allow_not_converged=True)
-        log(f"step {k + 1}/{a.steps}: {res[0]['iters']} iterations, {res[0]['certs']} certificates, "
+        log(f"step {k + 1}/{a.steps}: {max(r['iters'] for r in res)} iterations, {res[0]['certs']} certificates, "
             f"gaps " + " ".join(f"{r['rel_gap']:.1e}" for r in res))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -360,7 +360,7 @@ def bench_path_batched(a):
     cpu = None
     if a.cpu_cols > 0:
         try:
-            per = (seq_iters / a.npath) if seq_iters else res[0]["iters"]
+            per = (seq_iters / a.npath) if seq_iters else max(r["iters"] for r in res)
             cpu = cpu_baseline(spec, g, a.cpu_cols, per, p)
         except Exception as e:  # noqa: BLE001
             log(f"cpu baseline failed: {e}")
@@ -380,7 +380,7 @@ def bench_path_batched(a):
                    "parallelism": "single GPU"},
         "time_to_kkt_s_per_solve": elapsed / solves,
         "solves_converged": f"{conv}/{a.npath}",
-        "iterations": res[0]["iters"], "certificates": res[0]["certs"],
+        "iterations": max(r["iters"] for r in res), "certificates": res[0]["certs"],
         "setup_s": setup_s,
         "sequential_reference": seq,
         "speedup_vs_sequential": (seq["seconds"] / (elapsed / a.steps)) if seq else None,
@@ -438,7 +438,7 @@ def bench_batched(a):
     for k in range(a.steps):
         res = ctx.solve_batch(y, taus, lams, allow_not_converged=True)
         runs.append(res)
-        log(f"step {k + 1}/{a.steps}: {res[0]['iters']} iterations, {res[0]['certs']} certificates, "
+        log(f"step {k + 1}/{a.steps}: {max(r['iters'] for r in res)} iterations, {res[0]['certs']} certificates, "
             f"max gap {max(r['rel_gap'] for r in res):.2e}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -464,7 +464,7 @@ def bench_batched(a):
     cpu = None
     if a.cpu_cols > 0:
         try:
-            cpu = cpu_baseline(spec, g, a.cpu_cols, max(plain_iters, res[0]["iters"]) / K, p)
+            cpu = cpu_baseline(spec, g, a.cpu_cols, max(plain_iters, max(r["iters"] for r in res)) / K, p)
         except Exception as e:  # noqa: BLE001
             log(f"cpu baseline failed: {e}")
     out = {
@@ -483,7 +483,7 @@ def bench_batched(a):
                    "parallelism": "single GPU"},
         "time_to_kkt_s_all": elapsed / a.steps,
         "solves_converged": f"{conv}/{K}",
-        "iterations": res[0]["iters"],
+        "iterations": max(r["iters"] for r in res),
         "certificates": res[0]["certs"],
         "plain_path_s": plain_s, "plain_iterations": plain_iters,
         "plain_converged": f"{plain_conv}/{K}",

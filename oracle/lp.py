@@ -17,6 +17,14 @@ the Koenker-Bassett form extended by the penalty (lam_0 = 0: free intercept).
   independent kink hyperplanes, so the minimum over all such intersections is
   the optimum (exact rationals; p+1 <= 4).
 * ``highs``: scipy.optimize.linprog(method="highs") on the same LP in floats.
+
+The LP dual is  max y^T theta  s.t.  (tau-1)/n <= theta_i <= tau/n,
+|x_j^T theta| <= lam_j  (A^T theta <= c for A = [X1, -X1, I, -I]), the dual of the
+Lagrangian eq. main_lagrangian; ``simplex_exact(..., duals=True)`` returns its
+optimal theta as c_B^T B^-1 from the final tableau, ``highs_with_duals`` HiGHS's
+equality marginals, and ``highs_face_range`` the range of chosen coefficients over
+the optimal face (minimise and maximise beta_j subject to the objective staying at
+the optimum): a library-side test of the uniqueness of the minimiser.
 """
 from fractions import Fraction
 from itertools import combinations
@@ -82,8 +90,11 @@ def _simplex_phase(T, basis, cost, allowed):
         basis[best[1]] = enter
 
 
-def simplex_exact(c, A, b):
-    """Exact two-phase simplex.  Returns (optimal value, x) as Fractions."""
+def simplex_exact(c, A, b, duals=False):
+    """Exact two-phase simplex.  Returns (optimal value, x) as Fractions, and with
+    duals=True also the optimal dual y = c_B^T B^-1 of the equality rows (read from
+    the artificial columns of the final tableau, which hold B^-1 of the sign-adjusted
+    rows).  A holds an identity block here, so no row is ever redundant."""
     m, nv = len(A), len(c)
     T = []
     for i in range(m):
@@ -105,6 +116,8 @@ def simplex_exact(c, A, b):
             _pivot(T, i, col)
             basis[i] = col
         keep.append(i)
+    if duals and len(keep) != m:
+        raise RuntimeError("redundant equality rows: duals not defined by the tableau")
     T = [T[i] for i in keep]
     basis = [basis[i] for i in keep]
     cost2 = list(c) + [Fraction(0)] * m
@@ -115,7 +128,11 @@ def simplex_exact(c, A, b):
         if bi < nv:
             x[bi] = T[i][-1]
     val = sum(ci * xi for ci, xi in zip(c, x))
-    return val, x
+    if not duals:
+        return val, x
+    sgn = [-1 if bv < 0 else 1 for bv in b]
+    y = [sgn[i] * sum(cost2[basis[r]] * T[r][nv + i] for r in range(len(T))) for i in range(m)]
+    return val, x, y
 
 
 def objective_exact(X1, y, beta, tau, lam):
@@ -167,6 +184,32 @@ def vertex_enumeration(X1, y, tau, lam):
     return best
 
 
+def optimal_vertices(X1, y, tau, lam):
+    """Every distinct kink-hyperplane intersection attaining the minimum (exact).  The
+    minimiser set of the convex piecewise-linear P is a polyhedron whose vertices are
+    among these points; one point means a unique minimiser (when that set is
+    bounded, as it is whenever the design has full column rank)."""
+    n = len(y)
+    p1 = len(X1[0])
+    planes = [([_F(v) for v in X1[i]], _F(y[i])) for i in range(n)]
+    for j in range(1, p1):
+        if _F(lam[j]) > 0:
+            e = [Fraction(0)] * p1
+            e[j] = Fraction(1)
+            planes.append((e, Fraction(0)))
+    best, pts = None, set()
+    for sub in combinations(range(len(planes)), p1):
+        sol = _solve_exact([planes[s][0] for s in sub], [planes[s][1] for s in sub])
+        if sol is None:
+            continue
+        val = objective_exact(X1, y, sol, tau, lam)
+        if best is None or val < best:
+            best, pts = val, {tuple(sol)}
+        elif val == best:
+            pts.add(tuple(sol))
+    return best, sorted(pts)
+
+
 def highs(X1, y, tau, lam):
     """HiGHS (via scipy) on the same LP in floats.  Returns (value, beta)."""
     from scipy.optimize import linprog
@@ -184,3 +227,50 @@ def highs(X1, y, tau, lam):
         raise RuntimeError(res.message)
     x = res.x
     return float(res.fun), x[:p1] - x[p1:2 * p1]
+
+
+def _highs_lp(X1, y, tau, lam):
+    from scipy.sparse import csr_matrix, hstack, identity
+    X1 = np.asarray(X1, dtype=np.float64)
+    n, p1 = X1.shape
+    lam = np.asarray(lam, dtype=np.float64)
+    c = np.concatenate([lam, lam, np.full(n, tau / n), np.full(n, (1 - tau) / n)])
+    Xs = csr_matrix(X1)
+    A = hstack([Xs, -Xs, identity(n, format="csr"), -identity(n, format="csr")], format="csr")
+    return c, A, np.asarray(y, dtype=np.float64), p1
+
+
+_HIGHS_OPT = {"primal_feasibility_tolerance": 1e-10, "dual_feasibility_tolerance": 1e-10}
+
+
+def highs_with_duals(X1, y, tau, lam):
+    """HiGHS on the LP; returns (value, beta, theta) with theta the equality
+    marginals, i.e. an optimal point of the dual above."""
+    from scipy.optimize import linprog
+    c, A, b, p1 = _highs_lp(X1, y, tau, lam)
+    res = linprog(c, A_eq=A, b_eq=b, bounds=(0, None), method="highs", options=_HIGHS_OPT)
+    if res.status != 0:
+        raise RuntimeError(res.message)
+    x = res.x
+    return float(res.fun), x[:p1] - x[p1:2 * p1], np.asarray(res.eqlin.marginals, dtype=np.float64)
+
+
+def highs_face_range(X1, y, tau, lam, value, cols, rel=1e-9):
+    """For each j in cols: (min, max) of beta_j over {feasible, objective <= value (1 +
+    rel) + rel}, the optimal face widened by rel.  A face of width ~0 in every
+    coordinate means the minimiser is unique (up to the widening)."""
+    from scipy.optimize import linprog
+    c, A, b, p1 = _highs_lp(X1, y, tau, lam)
+    bound = value * (1 + rel) + rel
+    out = []
+    for j in cols:
+        e = np.zeros_like(c)
+        e[j], e[p1 + j] = 1.0, -1.0
+        lo = linprog(e, A_ub=c[None, :], b_ub=[bound], A_eq=A, b_eq=b, bounds=(0, None),
+                     method="highs", options=_HIGHS_OPT)
+        hi = linprog(-e, A_ub=c[None, :], b_ub=[bound], A_eq=A, b_eq=b, bounds=(0, None),
+                     method="highs", options=_HIGHS_OPT)
+        if lo.status != 0 or hi.status != 0:
+            raise RuntimeError(lo.message if lo.status else hi.message)
+        out.append((float(lo.fun), float(-hi.fun)))
+    return out

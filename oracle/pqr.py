@@ -344,8 +344,36 @@ def kkt_violation(X1, y, tau, lam, beta, theta, zero_tol=0.0):
                 intercept=float(abs(v[0])))
 
 
+def coef_uniqueness(X1, tau, lam, theta, margin=1e-7, rank_tol=1e-9):
+    """Is the minimiser unique?  theta must be an optimal dual point (the dual of the
+    Lagrangian eq. main_lagrangian: box (tau-1)/n <= theta_i <= tau/n, |x_j^T theta|
+    <= lam_j).  By complementary slackness (Prop. 1 with subgradients) every minimiser
+    beta' has beta'_j = 0 wherever |x_j^T theta| < lam_j and a zero residual
+    y_i = x_i^T beta' wherever theta_i lies strictly inside the box.  With J the
+    columns that may be nonzero (the intercept, unpenalized columns and those with
+    |x_j^T theta| >= lam_j (1 - margin)) and I the rows with theta_i at least
+    margin (hi - lo) inside the box, the minimiser is unique when X1[I, J] has full
+    column rank |J| (smallest singular value above rank_tol times the largest).  The
+    margins make the test conservative against the rounding of theta."""
+    X1 = np.asarray(X1, dtype=np.float64)
+    theta = np.asarray(theta, dtype=np.float64)
+    lam = np.asarray(lam, dtype=np.float64)
+    n = X1.shape[0]
+    lo, hi = (tau - 1.0) / n, tau / n
+    v = X1.T @ theta
+    J = np.nonzero((np.abs(v) >= lam * (1.0 - margin)) | (lam == 0))[0]
+    J = np.union1d([0], J)
+    w = margin * (hi - lo)
+    I = np.nonzero((theta > lo + w) & (theta < hi - w))[0]
+    if len(I) < len(J):
+        return dict(unique=False, J=J, I=I, sigma_min=0.0)
+    s = np.linalg.svd(X1[np.ix_(I, J)], compute_uv=False)
+    smin = float(s[-1]) if len(s) else 0.0
+    return dict(unique=bool(smin > rank_tol * max(1.0, float(s[0]))), J=J, I=I, sigma_min=smin)
+
+
 # ----------------------------------------------------------------------------
-# Standardisation (Sec. 6: standardised design, coefficients back-transformed)
+# Standardisation (Sec. 7: standardised design, coefficients back-transformed)
 # ----------------------------------------------------------------------------
 
 def standardize(X):

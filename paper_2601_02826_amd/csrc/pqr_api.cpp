@@ -1430,6 +1430,7 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
   const int smax = 16, min_per = 4;
   std::vector<double> best_dual(K, -INFINITY), primal(K, INFINITY), rel(K, INFINITY);
   std::vector<char> done(K, 0);
+  std::vector<int64_t> done_it(K, 0);   // iteration at which right-hand side k was certified
   int64_t it = 0, certs = 0;
   int ndone = 0;
   // convergence masks: a right-hand side whose certificate met tol_gap is frozen
@@ -1557,7 +1558,7 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
     }
     if (!fallback.empty()) TRY(certify_fp64(fallback));
     for (int k : ks)
-      if (rel[k] <= ctx->opt.tol_gap && !done[k]) { done[k] = 1; ++ndone; }
+      if (rel[k] <= ctx->opt.tol_gap && !done[k]) { done[k] = 1; done_it[k] = it; ++ndone; }
     return PQR_OK;
   };
   auto pending = [&]() {
@@ -1674,7 +1675,7 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
           for (int64_t i = 0; i < g.n; ++i) dst[i] = vf[i];
         }
       }
-      o->iters = it;
+      o->iters = done[k] ? done_it[k] : it;   // k is frozen once certified
       o->certs = certs;
       o->x_passes = it + certs;
       o->nnz = nnz;

@@ -452,3 +452,132 @@ def test_mlp_oracle_forward_closed_form():
     h2 = sil(2.0 * sil(0.5 * 1.2 - 0.1) + 0.25)
     out, _ = omlp.forward(prm, f)
     assert np.allclose(out[0], [-1.5 * h2 + 0.2, 0.75 * h2 - 0.3], rtol=1e-14, atol=1e-15)
+
+
+# ----------------------------------------------------------------------------
+# KKT report (Prop. 1 with subgradients) at an exact optimum, then with planted
+# violations of known size; exact LP duals; the uniqueness check
+# ----------------------------------------------------------------------------
+
+def _exact_optimum(seed, n, p, tau, lam_num):
+    """Integer data, an exact rational optimum (primal beta, dual theta) from the
+    simplex over Fractions, and its float copies."""
+    rng = np.random.default_rng(seed)
+    X = rng.integers(-3, 4, size=(n, p))
+    X1 = np.hstack([np.ones((n, 1), dtype=np.int64), X])
+    y = rng.integers(-6, 7, size=n)
+    tau_f = Fraction(tau).limit_denominator(100)
+    lam = [Fraction(0)] + [Fraction(lam_num, 10)] * p
+    c, A, b = lp.lp_data(X1.tolist(), y.tolist(), tau_f, lam)
+    val, x, th = lp.simplex_exact(c, A, b, duals=True)
+    p1 = p + 1
+    beta = [x[j] - x[p1 + j] for j in range(p1)]
+    return X1, y, tau_f, lam, val, beta, th
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_exact_duals_strong_duality_and_feasibility(seed):
+    """The simplex's dual is feasible for the dual of eq. main_lagrangian (box, zero sum,
+    |x_j^T theta| <= lam_j), exactly in rationals, and y^T theta equals the optimum."""
+    X1, y, tau, lam, val, beta, th = _exact_optimum(seed, 9, 3, 0.3, 2)
+    n = len(y)
+    assert sum(Fraction(int(y[i])) * th[i] for i in range(n)) == val
+    assert all((tau - 1) / n <= t <= tau / n for t in th)
+    for j in range(X1.shape[1]):
+        d = sum(Fraction(int(X1[i, j])) * th[i] for i in range(n))
+        assert (d == 0) if j == 0 else (abs(d) <= lam[j])
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_kkt_violation_zero_at_optimum_and_planted_sizes(seed):
+    X1, y, tau, lam, val, beta, th = _exact_optimum(seed, 10, 3, 0.4, 2)
+    n = len(y)
+    Xf, yf = X1.astype(np.float64), y.astype(np.float64)
+    lf = np.array([float(v) for v in lam])
+    b = np.array([float(v) for v in beta])
+    t = np.array([float(v) for v in th])
+    tf = float(tau)
+    k0 = pqr.kkt_violation(Xf, yf, tf, lf, b, t, zero_tol=1e-9)
+    assert max(k0.values()) < 1e-12
+    hi, lo = tf / n, (tf - 1) / n
+    r = yf - Xf @ b
+    delta = 0.37 / n
+    # a dual value pushed out of the box on a row with a positive, a negative and a
+    # zero residual: the box violation is exactly the push
+    for sel, val_t in [(r > 1e-9, hi + delta), (r < -1e-9, lo - delta), (np.abs(r) <= 1e-9, hi + delta)]:
+        rows = np.nonzero(sel)[0]
+        if len(rows) == 0:
+            continue
+        t2 = t.copy()
+        t2[rows[0]] = val_t
+        k = pqr.kkt_violation(Xf, yf, tf, lf, b, t2, zero_tol=1e-9)
+        assert k["dual_box"] == pytest.approx(delta, rel=1e-9)
+    # the sign of a nonzero penalized coefficient flipped: x_j^T theta = lam_j sign(beta_j)
+    # held, so the stationarity residual becomes 2 lam_j
+    nz = [j for j in range(1, len(b)) if b[j] != 0]
+    if nz:
+        b2 = b.copy()
+        b2[nz[0]] = -b2[nz[0]]
+        k = pqr.kkt_violation(Xf, yf, tf, lf, b2, t, zero_tol=1e-9)
+        assert k["stationarity"] == pytest.approx(2 * lf[nz[0]], rel=1e-12)
+    # a zero coefficient made positive: the residual is lam_j - x_j^T theta
+    zc = [j for j in range(1, len(b)) if b[j] == 0]
+    if zc:
+        j = zc[0]
+        vj = float(Xf[:, j] @ t)
+        b3 = b.copy()
+        b3[j] = 1e-3
+        k = pqr.kkt_violation(Xf, yf, tf, lf, b3, t, zero_tol=1e-9)
+        assert k["stationarity"] >= abs(vj - lf[j]) * (1 - 1e-12)
+        assert k["stationarity"] == pytest.approx(max(abs(vj - lf[j]), k0["stationarity"]), rel=1e-9)
+    # theta shifted by delta: the intercept's residual |sum theta| is n delta
+    k = pqr.kkt_violation(Xf, yf, tf, lf, b, t + delta, zero_tol=1e-9)
+    assert k["intercept"] == pytest.approx(n * delta, rel=1e-9)
+
+
+def test_uniqueness_check_against_exact_vertex_enumeration():
+    """coef_uniqueness (with the exact dual) agrees with the number of distinct optimal
+    vertices found by exact enumeration, on generic data and on planted degeneracy
+    (a duplicated column: beta_1 + beta_2 is fixed but its split is not)."""
+    seen = {True: 0, False: 0}
+    for seed in range(6):
+        X1, y, tau, lam, val, beta, th = _exact_optimum(seed, 6, 2, 0.3, 1)
+        if seed >= 3:   # duplicate column 1 into column 2
+            X1 = X1.copy()
+            X1[:, 2] = X1[:, 1]
+            c, A, b = lp.lp_data(X1.tolist(), y.tolist(), tau, lam)
+            val, x, th = lp.simplex_exact(c, A, b, duals=True)
+        best, pts = lp.optimal_vertices(X1.tolist(), y.tolist(), tau, lam)
+        assert best == val
+        u = pqr.coef_uniqueness(X1.astype(np.float64), float(tau), np.array([float(v) for v in lam]),
+                                np.array([float(v) for v in th]))
+        # the check is conservative: it may only claim uniqueness when it holds
+        if u["unique"]:
+            assert len(pts) == 1
+        if seed >= 3 and any(p[1] != 0 or p[2] != 0 for p in pts):
+            assert not u["unique"]
+        seen[u["unique"]] += 1
+    assert seen[True] >= 1 and seen[False] >= 1
+
+
+def test_uniqueness_check_against_highs_face_ranges():
+    """Generic Gaussian data: the check passes and HiGHS finds every coefficient's range
+    over the optimal face to be a point.  Intercept only with n tau an integer: the
+    check fails and the face range of beta_0 is [y_(n tau), y_(n tau + 1)] (closed form)."""
+    X1, y = _tiny(5, 40, 8)
+    tau = 0.5
+    lam = np.full(9, 0.2 * pqr.lambda_max(X1, y, tau))
+    lam[0] = 0.0
+    val, beta, th = lp.highs_with_duals(X1, y, tau, lam)
+    u = pqr.coef_uniqueness(X1, tau, lam, th)
+    assert u["unique"]
+    for (a, b) in lp.highs_face_range(X1, y, tau, lam, val, range(9), rel=1e-10):
+        assert b - a < 1e-6
+    # null model at lambda >= lambda_max with n tau integral: an interval of minimisers
+    lam2 = np.full(9, 1.5 * pqr.lambda_max(X1, y, tau))
+    lam2[0] = 0.0
+    val2, beta2, th2 = lp.highs_with_duals(X1, y, tau, lam2)
+    assert not pqr.coef_uniqueness(X1, tau, lam2, th2)["unique"]
+    (a, b), = lp.highs_face_range(X1, y, tau, lam2, val2, [0], rel=1e-12)
+    lo_q, hi_q = pqr.quantile_minimizers(y, tau)
+    assert a == pytest.approx(lo_q, abs=1e-7) and b == pytest.approx(hi_q, abs=1e-7)
