@@ -35,7 +35,7 @@ typedef enum {
   PQR_ERR_INVALID_ARG = 1,   /* bad size, tau outside (0,1), negative or non-finite input */
   PQR_ERR_OOM = 2,           /* device allocation failed */
   PQR_ERR_DEVICE = 3,        /* a HIP call failed */
-  PQR_ERR_NOT_CONVERGED = 4, /* max_iter reached; outputs hold the last iterate */
+  PQR_ERR_NOT_CONVERGED = 4, /* max_iter reached; outputs hold the best certified iterates */
   PQR_ERR_DIVERGED = 5,      /* the H-norm monitor tripped twice after eta was doubled */
   PQR_ERR_UNSUPPORTED = 6    /* combination of formats or options not provided */
 } pqr_status;
@@ -102,7 +102,13 @@ typedef struct pqr_ctx pqr_ctx;
  * caller (any may be NULL to skip it):
  *   beta      p+1 doubles, coefficients on the original scale (intercept first)
  *   beta_std  p+1 doubles, coefficients on the solver's (standardized) scale
- *   z, theta  n doubles each: the auxiliary and dual variables of Algorithm 1 */
+ *   z, theta  n doubles each: the auxiliary and dual variables of Algorithm 1
+ * The gap is certified from the best bounds seen at any certificate: beta,
+ * beta_std and z come from the evaluated iterate with the smallest P(beta), theta
+ * from the evaluated iterate whose feasible dual point had the largest dual value,
+ * so pqr_kkt(beta_std, theta) reproduces primal, dual and rel_gap.  (A warm start
+ * from such a result begins from these two iterates; PQR_START_DEVICE continues
+ * from the last iterate instead.) */
 typedef struct {
   double* beta;
   double* beta_std;
@@ -150,7 +156,7 @@ pqr_status pqr_create(pqr_ctx** out, const pqr_design* X, const pqr_options* opt
  *           may be NULL: then theta_i = (tau - 1{z_i < 0}) / n, centred so
  *           that sum(theta) = 0 (a subgradient of the check loss at z)
  *  out      results; see pqr_result.  On PQR_ERR_NOT_CONVERGED out still holds
- *           the last iterate and its certificate. */
+ *           the best certified iterates and their gap. */
 pqr_status pqr_solve(pqr_ctx* ctx, const double* y, double tau, double lambda,
                      const double* weights, int start, const pqr_result* warm,
                      pqr_result* out);
@@ -221,8 +227,10 @@ pqr_status pqr_solve_lla(pqr_ctx* ctx, const double* y, double tau, double lambd
  * entry so that it sums to zero exactly, the dual ratios x~_j^T theta_q exact in
  * integers from one int8 matrix-core pass for all due k (pqr_kkt's FP64 pass for a k
  * whose sum cannot be moved inside the box).  Needs an int8 store with codes 0..127,
- * rows_per_lane 16, FP32 iterates and positive weights (PQR_ERR_UNSUPPORTED
- * otherwise); 1 <= K <= 128.
+ * rows_per_lane 16, FP32 iterates, positive weights and, for the integer sums to
+ * stay exact in int32 with 32-bit buffer offsets, n_pad * max(max_code, 1) * 65 <
+ * 2^31 and 512 n_pad < 2^31, n_pad = n rounded up to a multiple of 1024
+ * (PQR_ERR_UNSUPPORTED otherwise); 1 <= K <= 128.
  *  y, weights  as in pqr_solve;  taus, lambdas  host, K doubles each
  *  outs        host array of K pqr_result (output arrays optional, as in pqr_solve);
  *              beta/z/theta are the final iterate, rel_gap its certified gap

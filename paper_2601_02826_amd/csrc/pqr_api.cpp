@@ -51,6 +51,8 @@ struct pqr_ctx {
          *gpart = nullptr, *partial64 = nullptr, *bpart64 = nullptr, *out_d = nullptr,
          *scratch64 = nullptr, *bt_out = nullptr;
   void* beta_best = nullptr;     // coefficients of the best primal iterate seen (iterate type)
+  void* z_best = nullptr;        // z of that iterate (n_pad, iterate type)
+  void* theta_best = nullptr;    // theta of the iterate with the best dual value (n_pad)
   int64_t bpart64_len = 0;
   double* out_h = nullptr;   // pinned
 
@@ -388,6 +390,8 @@ static pqr_status create_rest(pqr_ctx* ctx) {
   const size_t ts = tsize(ctx);
   TRY(dalloc(ctx, &ctx->beta, g.p_pad * ts));
   TRY(dalloc(ctx, &ctx->beta_best, g.p_pad * ts));
+  TRY(dalloc(ctx, &ctx->z_best, g.n_pad * ts));
+  TRY(dalloc(ctx, &ctx->theta_best, g.n_pad * ts));
   TRY(dalloc(ctx, &ctx->clam_t, g.p_pad * ts));
   TRY(dalloc(ctx, &ctx->cm_t, g.p_pad * ts));
   TRY(dalloc(ctx, &ctx->cinv_t, g.p_pad * ts));
@@ -755,9 +759,11 @@ pqr_status certificate(pqr_ctx* ctx, double tau, Cert* out) {
                           ctx->list, out);
 }
 
-// Copies the coefficients `bsrc` (intercept beta0) and the current z, theta out.
+// Copies the coefficients `bsrc` (intercept beta0), z from `zsrc` and theta from
+// `tsrc` out (device buffers of the iterate type).
 template <typename T>
-pqr_status export_state(pqr_ctx* ctx, pqr_result* res, const void* bsrc, double beta0) {
+pqr_status export_state(pqr_ctx* ctx, pqr_result* res, const void* bsrc, double beta0,
+                        const void* zsrc, const void* tsrc) {
   const Geom& g = ctx->g;
   hipStream_t s = ctx->s;
   Ctl c;
@@ -788,12 +794,12 @@ pqr_status export_state(pqr_ctx* ctx, pqr_result* res, const void* bsrc, double 
     HIPCHK(hipStreamSynchronize(s));
   }
   if (res->z) {
-    HIPCHK(launch_to_double<T>((const T*)ctx->z, g.n_pad, ctx->scratch64, s));
+    HIPCHK(launch_to_double<T>((const T*)zsrc, g.n_pad, ctx->scratch64, s));
     HIPCHK(hipMemcpyAsync(res->z, ctx->scratch64, g.n * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
   }
   if (res->theta) {
-    HIPCHK(launch_to_double<T>((const T*)ctx->theta, g.n_pad, ctx->scratch64, s));
+    HIPCHK(launch_to_double<T>((const T*)tsrc, g.n_pad, ctx->scratch64, s));
     HIPCHK(hipMemcpyAsync(res->theta, ctx->scratch64, g.n * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
   }
@@ -841,12 +847,18 @@ struct Run {
     Cert c{};
     TRY(certificate<T>(ctx, tau, &c));
     ++certs;
-    best_dual = std::max(best_dual, c.dual);
+    if (c.dual > best_dual) {
+      best_dual = c.dual;
+      HIPCHK(hipMemcpyAsync(ctx->theta_best, ctx->theta, ctx->g.n_pad * sizeof(T),
+                            hipMemcpyDeviceToDevice, ctx->s));
+    }
     if (c.primal < best_primal) {
       best_primal = c.primal;
       Ctl cc;
       HIPCHK(hipMemcpyAsync(&cc, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->s));
       HIPCHK(hipMemcpyAsync(ctx->beta_best, ctx->beta, ctx->g.p_pad * sizeof(T),
+                            hipMemcpyDeviceToDevice, ctx->s));
+      HIPCHK(hipMemcpyAsync(ctx->z_best, ctx->z, ctx->g.n_pad * sizeof(T),
                             hipMemcpyDeviceToDevice, ctx->s));
       HIPCHK(hipStreamSynchronize(ctx->s));
       best_beta0 = cc.beta0;
@@ -904,7 +916,7 @@ struct Run {
 
   pqr_status finish(pqr_result* out) {
     if (out) {
-      TRY(export_state<T>(ctx, out, ctx->beta_best, best_beta0));
+      TRY(export_state<T>(ctx, out, ctx->beta_best, best_beta0, ctx->z_best, ctx->theta_best));
       out->iters = it;
       out->certs = certs;
       out->x_passes = it + certs + 1;
@@ -1141,7 +1153,7 @@ pqr_status iterate_impl(pqr_ctx* ctx, const double* y, double tau, double lambda
   Ctl c;
   HIPCHK(hipMemcpyAsync(&c, ctx->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->s));
   HIPCHK(hipStreamSynchronize(ctx->s));
-  return export_state<T>(ctx, &r, ctx->beta, c.beta0);
+  return export_state<T>(ctx, &r, ctx->beta, c.beta0, ctx->z, ctx->theta);
 }
 }  // namespace
 
@@ -1393,6 +1405,16 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
   }
   if (ctx->max_code > 127) {
     ctx->err = "batched solves need int8 codes 0..127 (the store holds " +
+               std::to_string(ctx->max_code) + ")";
+    return PQR_ERR_UNSUPPORTED;
+  }
+  // Exactness limits of the integer products: an int32 matrix-core accumulator
+  // sums n_pad products code * digit with |digit| <= 64, and the digit buffers
+  // (up to 4 slices x 128 rows of n_pad bytes) are addressed with 32-bit offsets.
+  if ((int64_t)g.n_pad * std::max(ctx->max_code, 1) * 65 >= ((int64_t)1 << 31) ||
+      (int64_t)4 * 128 * g.n_pad >= ((int64_t)1 << 31)) {
+    ctx->err = "batched solves: n_pad * max_code * 65 and 512 * n_pad must stay below 2^31 "
+               "(n_pad " + std::to_string(g.n_pad) + ", max code " +
                std::to_string(ctx->max_code) + ")";
     return PQR_ERR_UNSUPPORTED;
   }

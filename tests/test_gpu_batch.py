@@ -70,3 +70,32 @@ def test_batch_rejects_unsupported_layouts():
         ctx.solve_batch(y, [0.5], [0.1])
     assert e.value.status == pq.PQR_ERR_UNSUPPORTED and "127" in str(e.value)
     ctx.close()
+
+
+def test_batch_rejects_sizes_beyond_exact_integer_range():
+    """The int32 matrix-core sums stay exact only while n_pad * max_code * 65 < 2^31,
+    and the digit buffers are addressed with 32-bit offsets (512 n_pad < 2^31): larger
+    designs are refused before any batched work."""
+    import torch
+    import paper_2601_02826_amd as pq
+    rng = np.random.default_rng(33)
+    # n = 270,000 rows with one code 127: 271,360 * 127 * 65 > 2^31
+    n, p = 270_000, 16
+    Xc = torch.from_numpy(rng.integers(0, 3, size=(p, n), dtype=np.uint8)).to("cuda:0")
+    Xc[3, 17] = 127
+    y = rng.standard_normal(n)
+    ctx = pq.Context.from_tensor(Xc, store_fmt="i8", G=1, rows_per_lane=16)
+    with pytest.raises(pq.PQRError) as e:
+        ctx.solve_batch(y, [0.5], [0.1])
+    assert e.value.status == pq.PQR_ERR_UNSUPPORTED and "2^31" in str(e.value)
+    ctx.close()
+    del Xc
+    # n_pad = 4,195,328 rows of dosages 0..2: 512 n_pad > 2^31
+    n = 4_194_305
+    Xc = torch.from_numpy(rng.integers(0, 3, size=(p, n), dtype=np.uint8)).to("cuda:0")
+    y = rng.standard_normal(n)
+    ctx = pq.Context.from_tensor(Xc, store_fmt="i8", G=1, rows_per_lane=16)
+    with pytest.raises(pq.PQRError) as e:
+        ctx.solve_batch(y, [0.5], [0.1])
+    assert e.value.status == pq.PQR_ERR_UNSUPPORTED and "2^31" in str(e.value)
+    ctx.close()
