@@ -233,7 +233,9 @@ pqr_status pqr_solve_lla(pqr_ctx* ctx, const double* y, double tau, double lambd
  * (PQR_ERR_UNSUPPORTED otherwise); 1 <= K <= 128.
  *  y, weights  as in pqr_solve;  taus, lambdas  host, K doubles each
  *  outs        host array of K pqr_result (output arrays optional, as in pqr_solve);
- *              beta/z/theta are the final iterate, rel_gap its certified gap
+ *              beta and z are the final iterate (a certified right-hand side stops
+ *              iterating), theta the iterate whose dual point gave the best dual value,
+ *              so primal, dual and rel_gap are reproduced from the exported beta, theta
  * Returns PQR_ERR_NOT_CONVERGED (outputs filled) if max_iter ends the solve first.
  * The single right-hand-side device state is discarded (PQR_START_DEVICE needs a
  * new pqr_solve afterwards). */

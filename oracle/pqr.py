@@ -133,6 +133,22 @@ def fsqrppa_step(X1, y, tau, lam, blocks, mu, eta, beta, z, theta):
     return beta_new, z_new, theta_new
 
 
+def fsqrppa_step_cached(X1, y, tau, lam, blocks, mu, eta, beta, z, theta, r):
+    """fsqrppa_step with r^k = X beta^k + z^k - y carried from the previous step (the
+    third line of eq. fsppa_update needs r^k, which the previous step computed), so a
+    step costs two products with X instead of three.  Returns (beta, z, theta, r)."""
+    n = X1.shape[0]
+    G = len(blocks)
+    beta_new = beta.copy()
+    for g, cols in enumerate(blocks):
+        v_g = X1[:, cols].T @ theta
+        beta_new[cols] = beta_prox(beta[cols], v_g, lam[cols], eta[g])
+    z_new = z_prox(z, theta, tau, n, mu)
+    r_new = X1 @ beta_new + z_new - y
+    theta_new = theta - (mu / (G + 1.0)) * (2.0 * r_new - r)
+    return beta_new, z_new, theta_new, r_new
+
+
 def h_norm_sq(X1, blocks, mu, eta, d_beta, d_z, d_theta):
     """||dw||_H^2 with H = [[D, A^T], [A, ((G+1)/mu) I]], D = diag(eta_g I, mu I),
     A = [X, I]: the metric in which the iteration is a proximal point step
@@ -283,20 +299,13 @@ def dual_certificate(X1, y, tau, lam, beta, theta):
                 theta_feasible=tf, alpha=alpha)
 
 
-def quantized_dual_certificate(X1, y, tau, lam, beta, theta, slices=4):
-    """Weak-duality certificate on an exactly representable dual point (Prop. 1 holds
-    for any point of the dual feasible set; the batched form's reading).  theta' is
-    the shift-and-clip projection of dual_certificate (positive weights only).  With
-    unit = c 2^-(7 slices - 1), c the power of two >= max(tau, 1 - tau)/n, the point
-    is theta_q = unit T with T = trunc(theta'/unit) (toward zero, so inside the box).
-    The integer sum of T is moved onto its largest entry (sum > 0) or its smallest
-    (sum < 0), the first index on ties, so that sum theta_q = 0 exactly; if that
-    entry would leave the box the function returns None.  Then alpha = min(1, min_j
-    lam_j / |x_j^T theta_q|) and the dual value is alpha y^T theta_q."""
-    n = X1.shape[0]
-    lam = np.asarray(lam, dtype=np.float64)
-    if np.any(lam[1:] <= 0):
-        raise ValueError("positive feature weights only")
+def quantize_dual_point(theta, tau, n, slices=4):
+    """The exactly representable dual point of the batched reading: theta' (the
+    shift-and-clip projection) truncated toward zero to theta_q = unit T, unit = c
+    2^-(7 slices - 1) with c the power of two >= max(tau, 1 - tau)/n, the integer sum
+    of T moved onto its largest entry (sum > 0) or smallest (sum < 0), first index on
+    ties.  Returns (theta_q, T, unit, t_lo, t_hi), or None when that entry would
+    leave the box."""
     lo, hi = (tau - 1.0) / n, tau / n
     tp = project_box_sum(theta, lo, hi)
     _, e = math.frexp(max(tau, 1.0 - tau) / n)
@@ -314,7 +323,36 @@ def quantized_dual_certificate(X1, y, tau, lam, beta, theta, slices=4):
         if T[i] - s > t_hi:
             return None
         T[i] -= s
-    tq = T.astype(np.float64) * unit
+    return T.astype(np.float64) * unit, T, unit, t_lo, t_hi
+
+
+def dual_value(y, t, max_ratio):
+    """Dual objective of the feasible point alpha t, alpha = min(1, 1/max_ratio), where
+    t is in the box with sum t = 0 and max_ratio = max_j |x_j^T t| / lam_j over the
+    penalized columns (the last step of dual_certificate, for ratios computed
+    elsewhere, e.g. column chunk by column chunk)."""
+    alpha = 1.0 if max_ratio <= 1.0 else (0.0 if math.isinf(max_ratio) else 1.0 / max_ratio)
+    return alpha * _sum(np.asarray(y, dtype=np.float64) * np.asarray(t, dtype=np.float64))
+
+
+def quantized_dual_certificate(X1, y, tau, lam, beta, theta, slices=4):
+    """Weak-duality certificate on an exactly representable dual point (Prop. 1 holds
+    for any point of the dual feasible set; the batched form's reading).  theta' is
+    the shift-and-clip projection of dual_certificate (positive weights only).  With
+    unit = c 2^-(7 slices - 1), c the power of two >= max(tau, 1 - tau)/n, the point
+    is theta_q = unit T with T = trunc(theta'/unit) (toward zero, so inside the box).
+    The integer sum of T is moved onto its largest entry (sum > 0) or its smallest
+    (sum < 0), the first index on ties, so that sum theta_q = 0 exactly; if that
+    entry would leave the box the function returns None.  Then alpha = min(1, min_j
+    lam_j / |x_j^T theta_q|) and the dual value is alpha y^T theta_q."""
+    n = X1.shape[0]
+    lam = np.asarray(lam, dtype=np.float64)
+    if np.any(lam[1:] <= 0):
+        raise ValueError("positive feature weights only")
+    q = quantize_dual_point(theta, tau, n, slices)
+    if q is None:
+        return None
+    tq, T, unit, t_lo, t_hi = q
     v = X1[:, 1:].T @ tq
     alpha = 1.0
     for vj, l in zip(np.abs(v), lam[1:]):

@@ -62,6 +62,7 @@ struct pqr_ctx {
   std::vector<hipEvent_t> events;   // 2 per iteration of a chunk when profiling
   int batch_kp = 0;                 // capacity of the batched buffers (right-hand sides)
   BatchBufs bb{};
+  float* btheta_best = nullptr;     // Kp x n_pad: per right-hand side, theta of its best dual
   double* w_d = nullptr;            // p_pad penalty weights in FP64 (batched certificates)
   float* yb = nullptr;              // n_pad y in FP32 (batched iterations)
   float* feats = nullptr;           // p_pad x 4 features of the scoring network
@@ -1338,6 +1339,7 @@ pqr_status batch_alloc(pqr_ctx* ctx, int Kp) {
   b.y = ctx->yb;
   TRY(dalloc(ctx, &b.z, (size_t)Kp * g.n_pad * 4));
   TRY(dalloc(ctx, &b.theta, (size_t)Kp * g.n_pad * 4));
+  TRY(dalloc(ctx, &ctx->btheta_best, (size_t)Kp * g.n_pad * 4));
   TRY(dalloc(ctx, &b.r, (size_t)Kp * g.n_pad * 4));
   TRY(dalloc(ctx, &b.dig, (size_t)3 * Kp * g.n_pad));
   TRY(dalloc(ctx, &b.tpart, (size_t)nblk * Kp * 8));
@@ -1497,13 +1499,20 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
     return PQR_OK;
   };
   // o = [primal loss, penalty, y^T theta, max ratio, ...]: alpha = min(1, 1 / ratio)
-  auto finish = [&](int k, const double* o) {
+  // The dual point of the best dual value is kept (its theta) so that the exported
+  // (beta, theta) reproduce the reported primal and dual values.
+  auto finish = [&](int k, const double* o) -> pqr_status {
     const double mr = o[3];
     const double alpha = mr > 1.0 ? (std::isinf(mr) ? 0.0 : 1.0 / mr) : 1.0;
     ++certs;
-    best_dual[k] = std::max(best_dual[k], alpha * o[2]);
+    if (alpha * o[2] > best_dual[k]) {
+      best_dual[k] = alpha * o[2];
+      HIPCHK(hipMemcpyAsync(ctx->btheta_best + (size_t)k * g.n_pad, b.theta + (size_t)k * g.n_pad,
+                            g.n_pad * 4, hipMemcpyDeviceToDevice, s));
+    }
     primal[k] = o[0] + o[1];
     rel[k] = (primal[k] - best_dual[k]) / std::max(std::fabs(primal[k]), 1e-300);
+    return PQR_OK;
   };
   // FP64 certificates, four right-hand sides per pass over X: the projections per
   // k, one shared pass for the dual ratios, then the sparse primal per k.  Same
@@ -1527,7 +1536,7 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
       for (int i = 0; i < kb; ++i) TRY(primal_of(ks[c0 + i], ctx->out4 + 8 * i));
       HIPCHK(hipMemcpyAsync(bout.data(), ctx->out4, 32 * 8, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      for (int i = 0; i < kb; ++i) finish(ks[c0 + i], bout.data() + 8 * i);
+      for (int i = 0; i < kb; ++i) TRY(finish(ks[c0 + i], bout.data() + 8 * i));
     }
     return PQR_OK;
   };
@@ -1575,7 +1584,7 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
       HIPCHK(hipStreamSynchronize(s));
       for (int i = 0; i < nk; ++i) {
         if (cout_h[8 * i + 7] != 0.0) fallback.push_back(ks[c0 + i]);
-        else finish(ks[c0 + i], cout_h.data() + 8 * i);
+        else TRY(finish(ks[c0 + i], cout_h.data() + 8 * i));
       }
     }
     if (!fallback.empty()) TRY(certify_fp64(fallback));
@@ -1691,7 +1700,7 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
         for (int which = 0; which < 2; ++which) {
           double* dst = which == 0 ? o->z : o->theta;
           if (!dst) continue;
-          const float* src = (which == 0 ? b.z : b.theta) + (size_t)k * g.n_pad;
+          const float* src = (which == 0 ? b.z : ctx->btheta_best) + (size_t)k * g.n_pad;
           HIPCHK(hipMemcpyAsync(vf.data(), src, g.n * 4, hipMemcpyDeviceToHost, s));
           HIPCHK(hipStreamSynchronize(s));
           for (int64_t i = 0; i < g.n; ++i) dst[i] = vf[i];

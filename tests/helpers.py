@@ -52,3 +52,39 @@ def random_state(n, p, seed, scale_beta=0.05, sparsity=0.05):
     z = rng.standard_normal(n) * 0.5
     theta = (rng.random(n) - 0.5) / n
     return beta, z, theta
+
+
+def host_pass(spec, thr, T, B=None, chunk=2048, workers=None):
+    """One FP64 pass over every column of the generated genotype design on the host:
+    the columns come from the host twin of the generator and are standardized by the
+    oracle (pqr.standardize, column by column), then V = X~^T T (p x K) and, with B
+    (p x K coefficients on the standardized scale), F = X~ B (n x K).  Chunks run in
+    a thread pool; F sums the chunks in column order (deterministic)."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    from threadpoolctl import threadpool_limits
+    from datagen import native
+    n, p = spec.n, spec.p
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    K = T.shape[1]
+    if workers is None:
+        workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    V = np.zeros((p, K))
+
+    def work(j0):
+        j1 = min(p, j0 + chunk)
+        X = native.genotype_host(n, j1 - j0, thr[j0:j1], spec.seed, spec.tag, j0=j0)
+        Xt, _, _ = pqr.standardize(X.astype(np.float64))
+        V[j0:j1] = Xt.T @ T
+        if B is None:
+            return None
+        Bc = B[j0:j1]
+        nz = np.nonzero(np.any(Bc != 0, axis=1))[0]
+        return Xt[:, nz] @ Bc[nz] if len(nz) else None
+
+    F = np.zeros((n, B.shape[1])) if B is not None else None
+    with threadpool_limits(1), ThreadPoolExecutor(workers) as ex:
+        for part in ex.map(work, range(0, p, chunk)):
+            if part is not None:
+                F += part
+    return V, F

@@ -94,6 +94,29 @@ def test_genotype_standardized_solve_and_back_transform(iter_prec, tol, coef_bou
     ctx.close()
 
 
+@pytest.mark.parametrize("store", ["fp8", "bf16", "2bit"])
+def test_store_formats_solve_to_the_lp_optimum(store):
+    """The 0/1/2 dosages are exact in FP8 E4M3, BF16 and 2-bit codes, so every store
+    format solves the same problem: certified 1e-6, objective within it of the unique
+    LP optimum, coefficients within the FP32 bound of the int8 store (2e-5)."""
+    n, p, G, tau = 600, 400, 3, 0.8
+    X, y = H.genotype_problem(n, p, seed=12)
+    X1, _, _ = H.oracle_design(X, True)
+    lam = 0.35 * pqr.lambda_max(X1, y, tau)
+    lam_vec = H.lam_vector(p, lam)
+    val, beta_lp = _unique_lp_optimum(X1, y, tau, lam_vec)
+    ctx = _ctx(X.astype(np.uint8), store_fmt=store, standardize=True, G=G, tol_gap=1e-6,
+               cert_every=200, max_iter=2_000_000)
+    r = ctx.solve(y, tau, lam)
+    p_gpu = pqr.objective(X1, y, r["beta_std"], tau, lam_vec)
+    err = np.max(np.abs(r["beta_std"] - beta_lp))
+    print(f"{store}: {r['iters']} iterations, gap {r['rel_gap']:.2e}, coefficient error {err:.2e}")
+    assert r["rel_gap"] <= 1e-6
+    assert val * (1 - 1e-12) <= p_gpu <= val * (1 + 1e-6) + 1e-12
+    assert err <= 2e-5
+    ctx.close()
+
+
 def test_lambda_path_with_device_warm_starts():
     n, p, G, tau = 500, 300, 3, 0.5
     X, y = H.genotype_problem(n, p, seed=13)

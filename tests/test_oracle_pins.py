@@ -293,6 +293,53 @@ def test_quantized_certificate_exact_feasibility_and_agreement(tau):
     assert val * (1 - 1e-6) <= cq["dual"] <= val + 1e-12
 
 
+def test_dual_value_from_chunked_ratios_bounds_the_optimum():
+    """dual_value (the certificate's last step, for ratios computed column chunk by
+    column chunk): the maximum ratio over chunks gives a feasible alpha t, so the value
+    bounds the LP optimum from below, reaches it at the exact optimal dual point, and
+    scaling is applied only when some ratio exceeds 1."""
+    n, p = 40, 9
+    X1, y = _tiny(21, n, p)
+    tau = 0.35
+    lam = np.full(p + 1, 0.2 * pqr.lambda_max(X1, y, tau))
+    lam[0] = 0.0
+    val, _, th = lp.highs_with_duals(X1, y, tau, lam)
+    rng = np.random.default_rng(4)
+    for _ in range(30):
+        t = pqr.project_box_sum(rng.standard_normal(n) * 0.05, (tau - 1) / n, tau / n)
+        ratios = [np.max(np.abs(X1[:, 1 + c].T @ t) / lam[1 + c]) for c in np.array_split(np.arange(p), 3)]
+        d = pqr.dual_value(y, t, max(ratios))
+        a = min(1.0, 1.0 / max(ratios))
+        assert np.max(np.abs(X1[:, 1:].T @ (a * t)) / lam[1:]) <= 1 + 1e-12
+        assert d <= val + 1e-12
+    assert pqr.dual_value(y, th, 0.5) == pytest.approx(float(y @ th), rel=1e-14)
+    r = np.max(np.abs(X1[:, 1:].T @ th) / lam[1:])
+    assert r <= 1 + 1e-8
+    assert pqr.dual_value(y, th, r) == pytest.approx(val, rel=1e-7)
+
+
+def test_cached_residual_step_equals_the_plain_step():
+    """Carrying r^k from the previous step is the same iteration (to rounding) as
+    recomputing it from (beta^k, z^k)."""
+    n, p = 50, 20
+    X1, y = _tiny(23, n, p)
+    tau = 0.3
+    lam = np.full(p + 1, 0.2 * pqr.lambda_max(X1, y, tau))
+    lam[0] = 0.0
+    blocks = pqr.partition(p, 3)
+    mu = pqr.default_mu(y, 3)
+    eta = pqr.step_sizes(X1, blocks, mu)
+    b, z, t = pqr.zero_start(y, p + 1)
+    b2, z2, t2 = b.copy(), z.copy(), t.copy()
+    r2 = X1 @ b2 + z2 - y
+    for _ in range(40):
+        b, z, t = pqr.fsqrppa_step(X1, y, tau, lam, blocks, mu, eta, b, z, t)
+        b2, z2, t2, r2 = pqr.fsqrppa_step_cached(X1, y, tau, lam, blocks, mu, eta, b2, z2, t2, r2)
+    assert np.allclose(b, b2, rtol=1e-10, atol=1e-13)
+    assert np.allclose(t, t2, rtol=1e-10, atol=1e-15)
+    assert np.allclose(r2, X1 @ b2 + z2 - y, atol=1e-12)
+
+
 def test_h_norm_successive_difference_non_increasing():
     X1, y = _tiny(4, 70, 40)
     tau, G = 0.5, 4
