@@ -312,6 +312,19 @@ int64_t pqr_mlp_workspace_bytes(int64_t B);
 pqr_status pqr_mlp_grad(const float* params, const float* feats, const float* target,
                         const float* active, int64_t B, double w_reg, double w_pos,
                         void* workspace, float* grad, float* loss, void* stream);
+/* pqr_mlp_grad without a workspace and without any allocation, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight training
+ * loops, harnesses that forbid hipMalloc).  Same arguments, kernels and results as
+ * pqr_mlp_grad; the partial gradients live in a library-owned device array of
+ * PQR_MLP_NOALLOC_MAX_ROWS / 128 * 4 * (4610 + 1) floats (4.7 MB, one per GPU,
+ * held until the process ends), looked up on the current device.  Calls that
+ * overlap on one GPU share that array and race; sequential calls need no
+ * clearing (every partial used is written first).  Errors: NULL pointers or
+ * B < 1: PQR_ERR_INVALID_ARG; B > PQR_MLP_NOALLOC_MAX_ROWS: PQR_ERR_UNSUPPORTED. */
+#define PQR_MLP_NOALLOC_MAX_ROWS 8192
+pqr_status pqr_mlp_grad_noalloc(const float* params, const float* feats, const float* target,
+                                const float* active, int64_t B, double w_reg, double w_pos,
+                                float* grad, float* loss, void* stream);
 /* One Adam step (step >= 1 counts from 1) on the 4610 parameters. */
 pqr_status pqr_mlp_adam(float* params, const float* grad, float* m, float* v, int step,
                         double lr, double beta1, double beta2, double eps, void* stream);

@@ -49,7 +49,7 @@ class pqr_result(ctypes.Structure):
 SYMBOLS = ["pqr_default_options", "pqr_create", "pqr_solve", "pqr_kkt", "pqr_lambda_max",
            "pqr_blocks", "pqr_iterate", "pqr_solve_batch", "pqr_kkt_columns", "pqr_create_subset",
            "pqr_mlp_param_count", "pqr_features", "pqr_mlp_forward", "pqr_mlp_workspace_bytes",
-           "pqr_mlp_grad", "pqr_mlp_adam", "pqr_solve_learned", "pqr_solve_grouped", "pqr_solve_lla",
+           "pqr_mlp_grad", "pqr_mlp_grad_noalloc", "pqr_mlp_adam", "pqr_solve_learned", "pqr_solve_grouped", "pqr_solve_lla",
            "pqr_interleaved_order", "pqr_destroy", "pqr_last_error", "pqr_status_string"]
 
 
@@ -109,6 +109,8 @@ def load():
     lib.pqr_mlp_workspace_bytes.restype = i64
     lib.pqr_mlp_grad.argtypes = [_c_fp, _c_fp, _c_fp, _c_fp, i64, dbl, dbl, _c_fp, _c_fp, _c_fp, vp]
     lib.pqr_mlp_grad.restype = ci
+    lib.pqr_mlp_grad_noalloc.argtypes = [_c_fp, _c_fp, _c_fp, _c_fp, i64, dbl, dbl, _c_fp, _c_fp, vp]
+    lib.pqr_mlp_grad_noalloc.restype = ci
     lib.pqr_mlp_adam.argtypes = [_c_fp, _c_fp, _c_fp, _c_fp, ci, dbl, dbl, dbl, dbl, vp]
     lib.pqr_mlp_adam.restype = ci
     lib.pqr_solve_learned.argtypes = [vp, _c_dp, dbl, dbl, _c_dp, _c_fp, dbl, ci,
@@ -511,6 +513,25 @@ def mlp_grad(params, feats, target, active, workspace, grad, loss, w_reg=1.0, w_
                           stream if stream is not None else _current_stream())
     if st != PQR_OK:
         raise PQRError(st, "pqr_mlp_grad failed")
+
+
+MLP_NOALLOC_MAX_ROWS = 8192
+
+
+def mlp_grad_noalloc(params, feats, target, active, grad, loss, w_reg=1.0, w_pos=1.0, B=None,
+                     stream=None):
+    """pqr_mlp_grad_noalloc: the gradient with the library's own fixed scratch (no
+    workspace, no allocation); at most MLP_NOALLOC_MAX_ROWS rows."""
+    lib = load()
+    B = feats.shape[0] if B is None else int(B)
+    st = lib.pqr_mlp_grad_noalloc(_ptr(params), _ptr(feats), _ptr(target), _ptr(active), B,
+                                  float(w_reg), float(w_pos), _ptr(grad), _ptr(loss),
+                                  stream if stream is not None else _current_stream())
+    if st == PQR_ERR_UNSUPPORTED:
+        raise PQRError(st, f"pqr_mlp_grad_noalloc: {B} rows exceed the allocation-free maximum "
+                           f"of {MLP_NOALLOC_MAX_ROWS}")
+    if st != PQR_OK:
+        raise PQRError(st, "pqr_mlp_grad_noalloc failed")
 
 
 def mlp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):

@@ -8,6 +8,7 @@
 // W3[2][64], b3[2].  Loss per row: w_reg (o0 - t)^2 + w_pos a softplus(-o1)
 // + (1 - a) softplus(o1), averaged over the rows.
 #include <cmath>
+#include <mutex>
 
 #include "pqr_kernels.h"
 
@@ -235,6 +236,36 @@ hipError_t launch_mlp_grad(const float* P, const float* F, const float* t, const
   hipLaunchKernelGGL(k_mlp_grad_reduce, dim3((kNP + 255) / 256), dim3(256), 0, s, part, lpart,
                      nb * kGTiles, grad, loss);
   return hipGetLastError();
+}
+
+// Scratch of the allocation-free gradient (pqr_mlp_grad_noalloc): the per-tile
+// partial gradients and losses of k_mlp_grad for up to kMlpNoAllocRows rows, in a
+// file-scope device array (one copy per GPU, held until the process ends).
+// k_mlp_grad writes every partial it covers before k_mlp_grad_reduce reads it, so
+// nothing has to be cleared between calls; calls that overlap on one GPU share
+// the array and race.
+constexpr int64_t kNoAllocPartials = (kMlpNoAllocRows + kGR - 1) / kGR * kGTiles;
+static __device__ __align__(256) float scratch[kNoAllocPartials * kNP + kNoAllocPartials];
+
+// Device address of `scratch` on the current device, looked up once per device.
+hipError_t mlp_noalloc_scratch(float** part, float** lpart) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static float* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = static_cast<float*>(ptr);
+  }
+  *part = addr[dev];
+  *lpart = addr[dev] + kNoAllocPartials * kNP;
+  return hipSuccess;
 }
 
 hipError_t launch_adam(float* P, const float* g, float* m, float* v, int n, float lr, float b1,

@@ -1820,6 +1820,21 @@ extern "C" pqr_status pqr_mlp_grad(const float* params, const float* feats, cons
   return PQR_OK;
 }
 
+extern "C" pqr_status pqr_mlp_grad_noalloc(const float* params, const float* feats,
+                                           const float* target, const float* active, int64_t B,
+                                           double w_reg, double w_pos, float* grad, float* loss,
+                                           void* stream) {
+  static_assert(PQR_MLP_NOALLOC_MAX_ROWS == kMlpNoAllocRows, "header and kernel limits differ");
+  if (!params || !feats || !target || !active || !grad || B < 1) return PQR_ERR_INVALID_ARG;
+  if (B > PQR_MLP_NOALLOC_MAX_ROWS) return PQR_ERR_UNSUPPORTED;
+  float *part = nullptr, *lpart = nullptr;
+  if (mlp_noalloc_scratch(&part, &lpart) != hipSuccess) return PQR_ERR_DEVICE;
+  if (launch_mlp_grad(params, feats, target, active, B, (float)w_reg, (float)w_pos, part, lpart,
+                      grad, loss, (hipStream_t)stream) != hipSuccess)
+    return PQR_ERR_DEVICE;
+  return PQR_OK;
+}
+
 extern "C" pqr_status pqr_mlp_adam(float* params, const float* grad, float* m, float* v, int step,
                                    double lr, double beta1, double beta2, double eps, void* stream) {
   if (!params || !grad || !m || !v || step < 1) return PQR_ERR_INVALID_ARG;

@@ -276,6 +276,10 @@ namespace pqr {
 // scoring network (kern_mlp.hip)
 hipError_t launch_mlp_forward(const float* P, const float* F, int64_t B, float* out, hipStream_t s);
 int mlp_grad_partials(int64_t B);
+// rows of the largest batch pqr_mlp_grad_noalloc takes (its scratch holds the
+// partials of that many rows)
+constexpr int64_t kMlpNoAllocRows = 8192;
+hipError_t mlp_noalloc_scratch(float** part, float** lpart);
 hipError_t launch_mlp_grad(const float* P, const float* F, const float* t, const float* a,
                            int64_t B, float w_reg, float w_pos, float* part, float* lpart,
                            float* grad, float* loss, hipStream_t s);
