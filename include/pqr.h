@@ -94,6 +94,15 @@ typedef struct {
                            Set through pqr_default_options; 0 is honoured as given. */
   int rows_per_lane;    /* 0 = automatic (16 when n >= 8192 or for 2-bit, else 4); 4 or 16
                            forces the row geometry (the batched solver needs 16) */
+  int launch_mode;      /* 0 (default) = pqr_solve replays each chunk of cert_every
+                           iterations as one captured HIP graph (captured on a private
+                           stream of the context, launched on `stream`; re-captured when
+                           the step parameters change); 1 = every kernel launched from
+                           the host.  Both run the same kernels in the same order.
+                           With opt.profile the kernels are always launched directly. */
+  int tile_override;    /* 0 (default) = batched solves choose their launch variants by
+                           timing them (pqr_batch_tiles); 1 + 3 b + a forces back-product
+                           variant b and union-product variant a (0..2 each), for tests */
 } pqr_options;
 
 typedef struct pqr_ctx pqr_ctx;
@@ -242,6 +251,18 @@ pqr_status pqr_solve_lla(pqr_ctx* ctx, const double* y, double tau, double lambd
 pqr_status pqr_solve_batch(pqr_ctx* ctx, const double* y, int K, const double* taus,
                            const double* lambdas, const double* weights, pqr_result* outs);
 
+/* The launch variants the autotuner chose for batched solves of width K on this
+ * context, and the mean time (ms) it measured for each of the three candidates of
+ * the back-product (bgemm_ms, host, 3 doubles; timed on the first batched solve of
+ * that width before its iterations) and of the union product (baxpy_ms; timed at the
+ * end of the first chunk of cert_every iterations whose union of nonzero columns
+ * holds at least 1024 columns, on that live union; baxpy_variant -1 if none has).  Variant 0 of each is the default configuration; every variant
+ * computes identical results.  union_cols receives the number of union columns the
+ * union product was timed on (0 if it was not).  Any output pointer may be NULL.
+ * PQR_ERR_INVALID_ARG if no batched solve of that width has run on ctx. */
+pqr_status pqr_batch_tiles(pqr_ctx* ctx, int K, int* bgemm_variant, int* baxpy_variant,
+                           double* bgemm_ms, double* baxpy_ms, int64_t* union_cols);
+
 /* Many independent problems (X_i, y_i, tau_i, lambda_i), one per context, solved
  * together from zero starts: every still-running problem takes one FS-QRPPA
  * iteration (Algorithm 1, eq. fsppa_update) per round of five grouped kernel
@@ -359,6 +380,23 @@ typedef struct {
 pqr_status pqr_solve_learned(pqr_ctx* ctx, const double* y, double tau, double lambda,
                              const double* weights, const float* params, double threshold,
                              int max_rounds, pqr_result* out, pqr_learned_report* rep);
+
+/* Screened warm start (the Discussion's screening direction, Sec. 8, made exact by
+ * the certificate; a non-learned counterpart of pqr_solve_learned): the sequential
+ * strong rule on the null-fit scores S_j of pqr_lambda_max proposes the active set
+ * A = {j : |S_j| >= (2 lambda - lambda_prev) w_j} (budget = 0; lambda_prev <= 0 means
+ * lambda_max), or the `budget` columns with the largest |S_j| / w_j (budget > 0);
+ * zero weights always join A, and an empty A starts from the 32 best scores.
+ * FS-QRPPA then solves the problem restricted to A from beta = 0, beta_0 = the
+ * tau-quantile of y, and the same rounds as pqr_solve_learned follow: the FP64
+ * certificate on the full design decides, columns outside A with |x~_j^T theta'| >
+ * lambda_j (1 + 1e-6) join A, and after max_rounds the plain zero-start solve
+ * answers.  The reported rel_gap is always the full design's certificate; rep is
+ * filled as for pqr_solve_learned.  Errors: max_rounds < 1, budget < 0 or a negative
+ * or non-finite lambda_prev: PQR_ERR_INVALID_ARG. */
+pqr_status pqr_solve_screened(pqr_ctx* ctx, const double* y, double tau, double lambda,
+                              const double* weights, double lambda_prev, int64_t budget,
+                              int max_rounds, pqr_result* out, pqr_learned_report* rep);
 
 void pqr_destroy(pqr_ctx* ctx);
 const char* pqr_last_error(const pqr_ctx* ctx);

@@ -411,6 +411,43 @@ def coef_uniqueness(X1, tau, lam, theta, margin=1e-7, rank_tol=1e-9):
 
 
 # ----------------------------------------------------------------------------
+# Screening (the Discussion's direction, Sec. 8): the sequential strong rule on the
+# null-fit scores, made exact by the dual check on every column
+# ----------------------------------------------------------------------------
+
+def strong_rule(score, lam, lam_prev, w=None):
+    """Columns kept by the sequential strong rule: |S_j| >= (2 lam - lam_prev) w_j, S_j
+    the null-fit score x_j^T psi / n (feature columns only, 0-based)."""
+    score = np.asarray(score, dtype=np.float64)
+    w = np.ones_like(score) if w is None else np.asarray(w, dtype=np.float64)
+    return np.nonzero(np.abs(score) >= (2.0 * lam - lam_prev) * w)[0]
+
+
+def screened_solve(X1, y, tau, lam, A, solve, max_rounds=20):
+    """Solve on the kept columns A (0-based feature indices), check every discarded
+    column's dual value |x_j^T theta| <= lam_j at the restricted optimum (Prop. 1),
+    add the violators and repeat.  `solve(X1r, y, tau, lamr)` returns (value, beta,
+    theta) of the restricted problem.  Returns (value, beta, theta, rounds, added)."""
+    p = X1.shape[1] - 1
+    A = np.array(sorted(set(int(j) for j in A)), dtype=np.int64)
+    added = 0
+    for rounds in range(1, max_rounds + 1):
+        cols = np.concatenate([[0], 1 + A])
+        val, bA, th = solve(X1[:, cols], y, tau, lam[cols])
+        v = np.abs(X1[:, 1:].T @ th)
+        out = np.ones(p, dtype=bool)
+        out[A] = False
+        viol = np.nonzero(out & (v > lam[1:] * (1.0 + 1e-9)))[0]
+        if len(viol) == 0:
+            beta = np.zeros(p + 1)
+            beta[cols] = bA
+            return val, beta, th, rounds, added
+        added += len(viol)
+        A = np.union1d(A, viol)
+    raise RuntimeError("screened_solve: violators remain after max_rounds")
+
+
+# ----------------------------------------------------------------------------
 # Standardisation (Sec. 7: standardised design, coefficients back-transformed)
 # ----------------------------------------------------------------------------
 

@@ -33,7 +33,8 @@ class pqr_options(ctypes.Structure):
                 ("iter_prec", ctypes.c_int), ("tol_gap", ctypes.c_double),
                 ("cert_every", ctypes.c_int), ("max_iter", ctypes.c_int64),
                 ("stream", ctypes.c_void_p), ("profile", ctypes.c_int),
-                ("intercept_block", ctypes.c_int), ("rows_per_lane", ctypes.c_int)]
+                ("intercept_block", ctypes.c_int), ("rows_per_lane", ctypes.c_int),
+                ("launch_mode", ctypes.c_int), ("tile_override", ctypes.c_int)]
 
 
 class pqr_result(ctypes.Structure):
@@ -47,9 +48,9 @@ class pqr_result(ctypes.Structure):
 
 
 SYMBOLS = ["pqr_default_options", "pqr_create", "pqr_solve", "pqr_kkt", "pqr_lambda_max",
-           "pqr_blocks", "pqr_iterate", "pqr_solve_batch", "pqr_kkt_columns", "pqr_create_subset",
+           "pqr_blocks", "pqr_iterate", "pqr_solve_batch", "pqr_batch_tiles", "pqr_kkt_columns", "pqr_create_subset",
            "pqr_mlp_param_count", "pqr_features", "pqr_mlp_forward", "pqr_mlp_workspace_bytes",
-           "pqr_mlp_grad", "pqr_mlp_grad_noalloc", "pqr_mlp_adam", "pqr_solve_learned", "pqr_solve_grouped", "pqr_solve_lla",
+           "pqr_mlp_grad", "pqr_mlp_grad_noalloc", "pqr_mlp_adam", "pqr_solve_learned", "pqr_solve_screened", "pqr_solve_grouped", "pqr_solve_lla",
            "pqr_interleaved_order", "pqr_destroy", "pqr_last_error", "pqr_status_string"]
 
 
@@ -91,6 +92,9 @@ def load():
     lib.pqr_iterate.restype = ci
     lib.pqr_solve_batch.argtypes = [vp, _c_dp, ci, _c_dp, _c_dp, _c_dp, ctypes.POINTER(pqr_result)]
     lib.pqr_solve_batch.restype = ci
+    lib.pqr_batch_tiles.argtypes = [vp, ci, ctypes.POINTER(ci), ctypes.POINTER(ci), _c_dp, _c_dp,
+                                    ctypes.POINTER(i64)]
+    lib.pqr_batch_tiles.restype = ci
     _c_fp = ctypes.c_void_p
     lib.pqr_kkt_columns.argtypes = [vp, _c_dp, dbl, dbl, _c_dp, _c_dp, _c_dp, _c_dp, _c_dp]
     lib.pqr_kkt_columns.restype = ci
@@ -116,6 +120,9 @@ def load():
     lib.pqr_solve_learned.argtypes = [vp, _c_dp, dbl, dbl, _c_dp, _c_fp, dbl, ci,
                                       ctypes.POINTER(pqr_result), ctypes.POINTER(pqr_learned_report)]
     lib.pqr_solve_learned.restype = ci
+    lib.pqr_solve_screened.argtypes = [vp, _c_dp, dbl, dbl, _c_dp, dbl, i64, ci,
+                                       ctypes.POINTER(pqr_result), ctypes.POINTER(pqr_learned_report)]
+    lib.pqr_solve_screened.restype = ci
     lib.pqr_solve_grouped.argtypes = [ci, ctypes.POINTER(vp), ctypes.POINTER(_c_dp), _c_dp, _c_dp,
                                       ctypes.POINTER(_c_dp), ctypes.POINTER(pqr_result),
                                       ctypes.POINTER(ci)]
@@ -282,6 +289,15 @@ class Context:
                               sweep_launches=o.sweep_launches, status=st))
         return res
 
+    def batch_tiles(self, K):
+        """pqr_batch_tiles: the autotuner's choices and candidate times for width K."""
+        bv, av, uc = ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
+        bms, ams = np.zeros(3), np.zeros(3)
+        self._check(self._lib.pqr_batch_tiles(self._h, int(K), ctypes.byref(bv), ctypes.byref(av),
+                                              _dptr(bms), _dptr(ams), ctypes.byref(uc)))
+        return dict(bgemm_variant=bv.value, baxpy_variant=av.value, bgemm_ms=bms.tolist(),
+                    baxpy_ms=ams.tolist(), union_cols=uc.value)
+
     def kkt_columns(self, y, tau, lam, beta_std, theta, weights=None):
         rep = np.zeros(4)
         v = np.zeros(self.p)
@@ -338,6 +354,30 @@ class Context:
                                          _dptr(_f64(weights, self.p + 1)),
                                          ctypes.c_void_p(int(params_ptr)), float(threshold),
                                          int(max_rounds), ctypes.byref(out), ctypes.byref(rep))
+        self._check(st, (PQR_OK, PQR_ERR_NOT_CONVERGED))
+        return Result(beta=beta, beta_std=beta_std, z=z, theta=theta, iters=out.iters, nnz=out.nnz,
+                      primal=out.primal, dual=out.dual, rel_gap=out.rel_gap,
+                      lambda_max=out.lambda_max, seconds=out.seconds, status=st,
+                      rounds=rep.rounds, fallback=rep.fallback, active_initial=rep.active_initial,
+                      active_final=rep.active_final, reduced_iters=rep.reduced_iters,
+                      seconds_proposal=rep.seconds_proposal, seconds_reduced=rep.seconds_reduced,
+                      seconds_check=rep.seconds_check, reduced_sweep_ms=rep.reduced_sweep_ms,
+                      reduced_sweep_bytes=rep.reduced_sweep_bytes,
+                      reduced_sweep_launches=rep.reduced_sweep_launches)
+
+    def solve_screened(self, y, tau, lam, lambda_prev=0.0, budget=0, max_rounds=4, weights=None):
+        """pqr_solve_screened: strong-rule (budget 0) or top-budget score proposal, then the
+        active-set rounds of the learned warm start, judged by the full certificate."""
+        beta = np.zeros(self.p + 1)
+        beta_std = np.zeros(self.p + 1)
+        z = np.zeros(self.n)
+        theta = np.zeros(self.n)
+        out = pqr_result(beta=_dptr(beta), beta_std=_dptr(beta_std), z=_dptr(z), theta=_dptr(theta))
+        rep = pqr_learned_report()
+        st = self._lib.pqr_solve_screened(self._h, _dptr(_f64(y, self.n)), float(tau), float(lam),
+                                          _dptr(_f64(weights, self.p + 1)), float(lambda_prev),
+                                          int(budget), int(max_rounds), ctypes.byref(out),
+                                          ctypes.byref(rep))
         self._check(st, (PQR_OK, PQR_ERR_NOT_CONVERGED))
         return Result(beta=beta, beta_std=beta_std, z=z, theta=theta, iters=out.iters, nnz=out.nnz,
                       primal=out.primal, dual=out.dual, rel_gap=out.rel_gap,

@@ -546,19 +546,27 @@ __global__ __launch_bounds__(256) void k_bbdigits(Geom g, BatchBufs b, int Kp) {
 
 // The product itself.  A wavefront owns 16 RT rows and every right-hand side;
 // per 64 union columns (one MFMA K step) it loads its rows of the 64 columns
-// (lane l: column l, 16 RT contiguous bytes), transposes them
-// through LDS into the B operand (lane: row l % 16, columns 16 (l / 16) .. +15),
-// and issues RT * NRT * 4 MFMAs with the coefficient digits as the A operand,
-// so that the result lands as (right-hand side, row) with rows contiguous.
-// Splits of the union along grid.y write FP64 partials.
+// (lane l: column l, 16 RT contiguous bytes), transposes them through LDS into
+// the B operand (lane: row l % 16, columns 16 (l / 16) .. +15), and issues
+// RT * NRT * 4 MFMAs with the coefficient digits as the A operand, so that the
+// result lands as (right-hand side, row) with rows contiguous.  The digits of a
+// step (NRT * 4 KB) are the same for every row: the WPB wavefronts of a block
+// stage them once per step in LDS (double-buffered, one barrier per step), so
+// the caches deliver them once per WPB * 16 RT rows instead of once per
+// wavefront.  Splits of the union along grid.y write FP64 partials.
 constexpr int kXStride = 68;   // LDS bytes per staged column (64 rows + 4, bank spread)
+constexpr int kAxPrefetch = 2; // 64-column steps loaded ahead of the union product's MFMAs
 
-template <int RT, int NRT>
-__global__ __launch_bounds__(256) void k_baxpy(Geom g, BatchBufs b, int smax, int min_per) {
+template <int RT, int NRT, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_baxpy(Geom g, BatchBufs b, int smax, int min_per) {
   constexpr int Kp = NRT * 16;
-  __shared__ uint32_t xs[4][64 * kXStride / 4];
-  const int lane = threadIdx.x & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  constexpr int kDig = NRT * kCS * 64;                  // uint4 digit fragments per step
+  constexpr int kDigPer = (kDig + 64 * WPB - 1) / (64 * WPB);
+  __shared__ uint32_t xs[WPB][64 * kXStride / 4];
+  __shared__ uint4 dg[2][kDig];                         // [buffer][(r * kCS + sl) * 64 + lane]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int count = *b.count;
   const int nq = (count + 63) / 64;                     // 64-column K steps of the union
   const int seff = bsplits(nq, smax, min_per);
@@ -567,8 +575,8 @@ __global__ __launch_bounds__(256) void k_baxpy(Geom g, BatchBufs b, int smax, in
                                                        // union still writes split 0)
   const int per = (nq + seff - 1) / seff;
   const int q0 = split * per, q1 = q0 + per < nq ? q0 + per : nq;
-  const int64_t rw = ((int64_t)blockIdx.x * 4 + wv) * (16 * RT);   // first row of the wave
-  const int64_t ch = rw >> 10, roff = rw & 1023;                   // 1024-row chunks
+  const int64_t rw = ((int64_t)blockIdx.x * WPB + wv) * (16 * RT);   // first row of the wave
+  const int64_t ch = rw >> 10, roff = rw & 1023;                     // 1024-row chunks
   v4i acc[RT][NRT][kCS];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
@@ -579,36 +587,57 @@ __global__ __launch_bounds__(256) void k_baxpy(Geom g, BatchBufs b, int smax, in
   uint32_t* xw = xs[wv];
   const int kb = lane >> 4, m = lane & 15;
   const int nvg = (count + 15) / 16;                    // virtual groups with digits
-  // Loads of one 64-column step: this lane's rows of union entry 64 qd + lane (past
-  // the count it re-reads the last entry) and the A operand, the digits of (rhs
-  // r*16 + m, virtual group 4 qd + kb) (past the last virtual group it re-reads
-  // the last one and zeroes it).  All loads are unconditional; the next step's
-  // are issued before this step's MFMAs.
-  auto fetch = [&](int qd, uint4 (&xv)[RT], v4i (&af)[NRT][kCS]) {
+  // This thread's rows of union entry 64 qd + lane (past the count it re-reads the
+  // last entry; its digits are zero).
+  auto fetch_x = [&](int qd, uint4 (&xv)[RT]) {
     const int il = 64 * qd + lane < count ? 64 * qd + lane : count - 1;
     const int64_t jl = b.list[il];
     const uint8_t* src = g.seg(jl, ch) + roff;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) xv[rt] = *reinterpret_cast<const uint4*>(src + 16 * rt);
-    const int el = 4 * qd + kb;
-    const bool live = el < nvg;
-    const int64_t ec = live ? el : nvg - 1;
-#pragma unroll
-    for (int r = 0; r < NRT; ++r)
-#pragma unroll
-      for (int sl = 0; sl < kCS; ++sl) {
-        const uint4 v = *reinterpret_cast<const uint4*>(
-            b.bd + (((int64_t)ec * Kp + r * 16 + m) * kCS + sl) * kGroup);
-        af[r][sl] = live ? v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w} : v4i{0, 0, 0, 0};
-      }
   };
+  // This thread's share of the step's digits: fragment f = (r * kCS + sl) * 64 + l
+  // holds the A operand of MFMA lane l: digits of (rhs r*16 + l % 16, virtual group
+  // 4 qd + l / 16), zero past the last virtual group.
+  auto fetch_d = [&](int qd, uint4 (&dv)[kDigPer]) {
+#pragma unroll
+    for (int u = 0; u < kDigPer; ++u) {
+      const int f = tid + u * 64 * WPB;
+      const int fl = f < kDig ? f : 0;
+      const int l = fl & 63, sl = (fl >> 6) % kCS, r = (fl >> 6) / kCS;
+      const int el = 4 * qd + (l >> 4);
+      const int64_t ec = el < nvg ? el : nvg - 1;
+      const uint4 v = *reinterpret_cast<const uint4*>(
+          b.bd + (((int64_t)ec * Kp + r * 16 + (l & 15)) * kCS + sl) * kGroup);
+      dv[u] = el < nvg ? v : uint4{0, 0, 0, 0};
+    }
+  };
+  auto store_d = [&](int buf, const uint4 (&dv)[kDigPer]) {
+#pragma unroll
+    for (int u = 0; u < kDigPer; ++u) {
+      const int f = tid + u * 64 * WPB;
+      if (f < kDig) dg[buf][f] = dv[u];
+    }
+  };
+  // Loads run NPF steps ahead of the MFMAs (xq[i], dq[i]: step qd + 1 + i), so that
+  // NPF + 1 steps of X are in flight per wavefront across the block's barriers.
   uint4 xv[RT];
-  v4i af[NRT][kCS];
-  if (q0 < q1) fetch(q0, xv, af);
+  uint4 xq[kAxPrefetch][RT];
+  uint4 dq[kAxPrefetch][kDigPer];
+  if (q0 < q1) {
+    uint4 d0[kDigPer];
+    fetch_x(q0, xv);
+    fetch_d(q0, d0);
+    store_d(q0 & 1, d0);
+#pragma unroll
+    for (int i = 0; i < kAxPrefetch; ++i) {
+      const int qi = q0 + 1 + i < q1 ? q0 + 1 + i : q1 - 1;
+      fetch_x(qi, xq[i]);
+      fetch_d(qi, dq[i]);
+    }
+  }
+  __syncthreads();
   for (int qd = q0; qd < q1; ++qd) {
-    uint4 xn[RT];
-    v4i an[NRT][kCS];
-    fetch(qd + 1 < q1 ? qd + 1 : qd, xn, an);
     // stage: column `lane` at xw[lane * kXStride / 4 ...], rows 0 .. 16 RT - 1
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
@@ -617,6 +646,8 @@ __global__ __launch_bounds__(256) void k_baxpy(Geom g, BatchBufs b, int smax, in
     }
     __builtin_amdgcn_wave_barrier();
     const uint8_t* xb = reinterpret_cast<const uint8_t*>(xw);
+    const uint4* dgb = dg[qd & 1];
+    v4i bf[RT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
       // B operand: row 16 rt + m, columns 16 kb + 0..15
@@ -627,20 +658,37 @@ __global__ __launch_bounds__(256) void k_baxpy(Geom g, BatchBufs b, int smax, in
         w[q] = (uint32_t)p[0] | ((uint32_t)p[kXStride] << 8) | ((uint32_t)p[2 * kXStride] << 16) |
                ((uint32_t)p[3 * kXStride] << 24);
       }
-      const v4i bf = v4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
-#pragma unroll
-      for (int r = 0; r < NRT; ++r)
-#pragma unroll
-        for (int sl = 0; sl < kCS; ++sl)
-          acc[rt][r][sl] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[r][sl], bf, acc[rt][r][sl], 0, 0, 0);
+      bf[rt] = v4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
     }
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt) xv[rt] = xn[rt];
 #pragma unroll
     for (int r = 0; r < NRT; ++r)
 #pragma unroll
-      for (int sl = 0; sl < kCS; ++sl) af[r][sl] = an[r][sl];
+      for (int sl = 0; sl < kCS; ++sl) {
+        const uint4 a4 = dgb[(r * kCS + sl) * 64 + lane];
+        const v4i af = v4i{(int)a4.x, (int)a4.y, (int)a4.z, (int)a4.w};
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+          acc[rt][r][sl] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf[rt], acc[rt][r][sl], 0, 0, 0);
+      }
+    __builtin_amdgcn_wave_barrier();
+    // every wavefront has finished reading buffer (qd + 1) & 1 (step qd - 1) before
+    // the barrier that ended that step, so it can be refilled now
+    store_d((qd + 1) & 1, dq[0]);
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) xv[rt] = xq[0][rt];
+#pragma unroll
+    for (int i = 0; i + 1 < kAxPrefetch; ++i) {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) xq[i][rt] = xq[i + 1][rt];
+#pragma unroll
+      for (int u = 0; u < kDigPer; ++u) dq[i][u] = dq[i + 1][u];
+    }
+    {
+      const int qf = qd + 1 + kAxPrefetch < q1 ? qd + 1 + kAxPrefetch : q1 - 1;
+      fetch_x(qf, xq[kAxPrefetch - 1]);
+      fetch_d(qf, dq[kAxPrefetch - 1]);
+    }
+    __syncthreads();
   }
   // lane holds C[rhs = r*16 + 4 kb + i][row = rw + 16 rt + m]
 #pragma unroll
@@ -867,53 +915,117 @@ hipError_t launch_cert_pass(const Geom& g, const CertArgs& c, int Kc, hipStream_
 }
 
 // ---------------------------------------------------------------------------
+// Launch variants the batched solve's autotuner times per batch width.  Back-
+// product: variant 0 is the configuration chosen per tile count (one or two tiles
+// per wavefront, GW = 4 groups, GW * TW * S * 4 <= 96 accumulators; wps = wavefronts
+// sharing a set of groups; blocks of 8 wavefronts, so that at about 200 VGPRs one
+// block fills a CU and a staged digit tile serves 8 GW / wps groups; with 3 to 8
+// tiles the set's A fragments are staged once in LDS too), variant 1 the same with
+// GW = 2 (half the accumulators, twice the blocks), variant 2 for 1 or 2 tiles a
+// longer digit tile (SPT 4, one barrier per 256 rows) or the shared-A form.
+// DL = ceil(12 SPT Kp / (64 WPB)) digit loads per thread and tile.
+int bgemm_variants() { return 3; }
+
+hipError_t launch_bgemm_variant(const Geom& g, const BatchBufs& b, int Kp, int v, hipStream_t s,
+                                hipEvent_t ev0, hipEvent_t ev1) {
+  const CertArgs c{};
+  const int nrt = Kp / 16;
+  if (v < 0 || v > 2) return hipErrorInvalidValue;
+  switch (nrt) {
+    case 1:
+      if (v == 0) return launch_bgemm<1, 4, 1, 2, 8, 2, kBS, false>(g, b, c, Kp, 1, s, ev0, ev1);
+      if (v == 1) return launch_bgemm<1, 2, 1, 2, 8, 2, kBS, false>(g, b, c, Kp, 1, s, ev0, ev1);
+      return launch_bgemm<1, 4, 2, 4, 8, 2, kBS, false>(g, b, c, Kp, 1, s, ev0, ev1);
+    case 2:
+      if (v == 0) return launch_bgemm<2, 4, 2, 2, 8, 2, kBS, false>(g, b, c, Kp, 1, s, ev0, ev1);
+      if (v == 1) return launch_bgemm<2, 2, 2, 2, 8, 2, kBS, false>(g, b, c, Kp, 1, s, ev0, ev1);
+      return launch_bgemm<1, 4, 2, 2, 8, 2, kBS, false, true>(g, b, c, Kp, 2, s, ev0, ev1);
+    case 3:
+    case 4:
+      if (v == 1) return launch_bgemm<2, 2, 3, 2, 8, 2, kBS, false, true>(g, b, c, Kp, 2, s, ev0, ev1);
+      return launch_bgemm<2, 4, 3, 2, 8, 2, kBS, false, true>(g, b, c, Kp, 2, s, ev0, ev1);
+    case 5:
+      if (v == 1) return launch_bgemm<2, 2, 4, 2, 8, 2, kBS, false, true>(g, b, c, Kp, 4, s, ev0, ev1);
+      return launch_bgemm<2, 4, 4, 2, 8, 2, kBS, false, true>(g, b, c, Kp, 4, s, ev0, ev1);
+    case 6:
+    case 7:
+    case 8:
+      if (v == 1) return launch_bgemm<2, 2, 6, 2, 8, 2, kBS, false, true>(g, b, c, Kp, 4, s, ev0, ev1);
+      return launch_bgemm<2, 4, 6, 2, 8, 2, kBS, false, true>(g, b, c, Kp, 4, s, ev0, ev1);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Union product: rows per wavefront 16 RT with RT * NRT * 16 <= 128 accumulator
+// registers; variants 0, 1, 2 = blocks of 8, 4 and 16 wavefronts sharing the staged
+// digits (n_pad is a multiple of 1024 >= 16 W RT rows); splits of the union along y.
+int baxpy_variants() { return 3; }
+
+template <int W>
+static hipError_t launch_baxpy_w(const Geom& g, const BatchBufs& b, int nrt, int smax, int min_per,
+                                 hipStream_t s) {
+  const unsigned smx = (unsigned)smax;
+  auto rows = [&](int rt) { return dim3((unsigned)(g.n_pad / (16 * W * rt)), smx); };
+  const dim3 blk(64 * W);
+  switch (nrt) {
+    case 1: hipLaunchKernelGGL((k_baxpy<4, 1, W>), rows(4), blk, 0, s, g, b, smax, min_per); break;
+    case 2: hipLaunchKernelGGL((k_baxpy<2, 2, W>), rows(2), blk, 0, s, g, b, smax, min_per); break;
+    case 3: hipLaunchKernelGGL((k_baxpy<1, 3, W>), rows(1), blk, 0, s, g, b, smax, min_per); break;
+    case 4: hipLaunchKernelGGL((k_baxpy<1, 4, W>), rows(1), blk, 0, s, g, b, smax, min_per); break;
+    case 5: hipLaunchKernelGGL((k_baxpy<1, 5, W>), rows(1), blk, 0, s, g, b, smax, min_per); break;
+    case 6: hipLaunchKernelGGL((k_baxpy<1, 6, W>), rows(1), blk, 0, s, g, b, smax, min_per); break;
+    case 7: hipLaunchKernelGGL((k_baxpy<1, 7, W>), rows(1), blk, 0, s, g, b, smax, min_per); break;
+    case 8: hipLaunchKernelGGL((k_baxpy<1, 8, W>), rows(1), blk, 0, s, g, b, smax, min_per); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// 16-wavefront blocks cap a wavefront at 128 VGPRs, which from 5 tiles on would spill
+// the accumulators: there variant 2 is the 8-wavefront block.
+template <>
+hipError_t launch_baxpy_w<16>(const Geom& g, const BatchBufs& b, int nrt, int smax, int min_per,
+                              hipStream_t s) {
+  const dim3 blk(64 * 16);
+  auto rows = [&](int rt) { return dim3((unsigned)(g.n_pad / (16 * 16 * rt)), (unsigned)smax); };
+  switch (nrt) {
+    case 1: hipLaunchKernelGGL((k_baxpy<4, 1, 16>), rows(4), blk, 0, s, g, b, smax, min_per); break;
+    case 2: hipLaunchKernelGGL((k_baxpy<2, 2, 16>), rows(2), blk, 0, s, g, b, smax, min_per); break;
+    case 3: hipLaunchKernelGGL((k_baxpy<1, 3, 16>), rows(1), blk, 0, s, g, b, smax, min_per); break;
+    case 4: hipLaunchKernelGGL((k_baxpy<1, 4, 16>), rows(1), blk, 0, s, g, b, smax, min_per); break;
+    default: return launch_baxpy_w<8>(g, b, nrt, smax, min_per, s);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_baxpy_variant(const Geom& g, const BatchBufs& b, int Kp, int smax, int min_per,
+                                int v, hipStream_t s) {
+  if (g.n_pad % 1024) return hipErrorInvalidValue;
+  const int nrt = Kp / 16;
+  if (v == 0) return launch_baxpy_w<8>(g, b, nrt, smax, min_per, s);
+  if (v == 1) return launch_baxpy_w<4>(g, b, nrt, smax, min_per, s);
+  if (v == 2) return launch_baxpy_w<16>(g, b, nrt, smax, min_per, s);
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_batch_iteration(const Geom& g, const BatchBufs& b, int Kp, double mu,
                                   double sigma, double eta0, int smax, int min_per,
-                                  hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                                  const BatchTiles& tiles, hipStream_t s, hipEvent_t ev0,
+                                  hipEvent_t ev1) {
   if (g.fmt != I8 || g.rpl != 16 || Kp % 16 || Kp > 128) return hipErrorInvalidValue;
   const unsigned nb = (unsigned)(g.n_pad / 256);
   const int nrt = Kp / 16;
   hipLaunchKernelGGL(k_bdigits, dim3(nb, Kp), dim3(256), 0, s, b, g.n, g.n_pad, Kp);
   hipLaunchKernelGGL(k_bdsum, dim3(1), dim3(128), 0, s, b, (int)nb, Kp);
-  // One or two tiles per wavefront, GW = 4 groups (GW * TW * S * 4 <= 96 accumulators);
-  // wps = wavefronts sharing a set of groups (1, 2 or 4).  Blocks of 8 wavefronts:
-  // at about 200 VGPRs one block fills a CU, so two digit tiles of up to 128 KB of
-  // LDS cost no occupancy, and a staged tile serves 8 GW / wps groups.  128-row
-  // digit tiles; with 3 to 8 tiles (wps >= 2) the set's A fragments are staged
-  // once in LDS too (shared A) instead of being loaded by each of its wavefronts.
-  hipError_t e = hipSuccess;
-  switch (nrt) {   // DL = ceil(12 SPT Kp / (64 WPB)) digit loads per thread and tile
-    case 1: e = launch_bgemm<1, 4, 1, 2, 8, 2, kBS, false>(g, b, CertArgs{}, Kp, 1, s, ev0, ev1); break;
-    case 2: e = launch_bgemm<2, 4, 2, 2, 8, 2, kBS, false>(g, b, CertArgs{}, Kp, 1, s, ev0, ev1); break;
-    case 3: e = launch_bgemm<2, 4, 3, 2, 8, 2, kBS, false, true>(g, b, CertArgs{}, Kp, 2, s, ev0, ev1); break;
-    case 4: e = launch_bgemm<2, 4, 3, 2, 8, 2, kBS, false, true>(g, b, CertArgs{}, Kp, 2, s, ev0, ev1); break;
-    case 5: e = launch_bgemm<2, 4, 4, 2, 8, 2, kBS, false, true>(g, b, CertArgs{}, Kp, 4, s, ev0, ev1); break;
-    case 6: e = launch_bgemm<2, 4, 6, 2, 8, 2, kBS, false, true>(g, b, CertArgs{}, Kp, 4, s, ev0, ev1); break;
-    case 7: e = launch_bgemm<2, 4, 6, 2, 8, 2, kBS, false, true>(g, b, CertArgs{}, Kp, 4, s, ev0, ev1); break;
-    case 8: e = launch_bgemm<2, 4, 6, 2, 8, 2, kBS, false, true>(g, b, CertArgs{}, Kp, 4, s, ev0, ev1); break;
-  }
+  hipError_t e = launch_bgemm_variant(g, b, Kp, tiles.bgemm, s, ev0, ev1);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_bcount, dim3(kCompactBlocks), dim3(1024), 0, s, g.ngroups(), b, nrt);
   hipLaunchKernelGGL(k_bscatter, dim3(kCompactBlocks), dim3(1024), 0, s, g.ngroups(), b, nrt,
                      eta0, Kp);
   hipLaunchKernelGGL(k_bbmax, dim3(kDigitBlocks), dim3(256), 0, s, g, b, Kp);
   hipLaunchKernelGGL(k_bbdigits, dim3(kDigitBlocks), dim3(256), 0, s, g, b, Kp);
-  // rows per wavefront 16 RT with RT * NRT * 16 <= 128 accumulator registers;
-  // blocks of 4 wavefronts, splits of the union along y
-  {
-    const unsigned smx = (unsigned)smax;
-    auto rows = [&](int rt) { return dim3((unsigned)(g.n_pad / (64 * rt)), smx); };
-    switch (nrt) {
-      case 1: hipLaunchKernelGGL((k_baxpy<4, 1>), rows(4), dim3(256), 0, s, g, b, smax, min_per); break;
-      case 2: hipLaunchKernelGGL((k_baxpy<2, 2>), rows(2), dim3(256), 0, s, g, b, smax, min_per); break;
-      case 3: hipLaunchKernelGGL((k_baxpy<1, 3>), rows(1), dim3(256), 0, s, g, b, smax, min_per); break;
-      case 4: hipLaunchKernelGGL((k_baxpy<1, 4>), rows(1), dim3(256), 0, s, g, b, smax, min_per); break;
-      case 5: hipLaunchKernelGGL((k_baxpy<1, 5>), rows(1), dim3(256), 0, s, g, b, smax, min_per); break;
-      case 6: hipLaunchKernelGGL((k_baxpy<1, 6>), rows(1), dim3(256), 0, s, g, b, smax, min_per); break;
-      case 7: hipLaunchKernelGGL((k_baxpy<1, 7>), rows(1), dim3(256), 0, s, g, b, smax, min_per); break;
-      case 8: hipLaunchKernelGGL((k_baxpy<1, 8>), rows(1), dim3(256), 0, s, g, b, smax, min_per); break;
-    }
-  }
+  e = launch_baxpy_variant(g, b, Kp, smax, min_per, tiles.baxpy, s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_bupdate, dim3(nb, Kp), dim3(256), 0, s, b, g.n, g.n_pad, Kp, mu, sigma,
                      smax, min_per);
   hipLaunchKernelGGL(k_bfinal, dim3(1), dim3(128), 0, s, b, (int)nb, Kp);

@@ -276,8 +276,7 @@ __global__ __launch_bounds__(256) void k_loss64(CertBufs c, int64_t n, int64_t n
   const int seff = splits_in_use64(c.ctl->count, smax, min_per);
   double q[1] = {0.0};
   if (i < n) {
-    double s = c.ctl->beta0;
-    for (int k = 0; k < seff; ++k) s += c.partial[(int64_t)k * n_pad + i];
+    const double s = sum_splits(c.partial, seff, n_pad, i, c.ctl->beta0);
     const double r = c.y[i] - s;
     q[0] = (r < 0 ? tau - 1.0 : tau) * r;
   }

@@ -263,8 +263,7 @@ __device__ __forceinline__ void update_body(const IterBufs<T>& b, const IterPara
   const int seff = splits_in_use(b.ctl->count, ip.smax, ip.min_per);
   double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (i < n) {
-    double s = b.ctl->beta0;
-    for (int k = 0; k < seff; ++k) s += b.partial[(int64_t)k * n_pad + i];
+    const double s = sum_splits(b.partial, seff, n_pad, i, b.ctl->beta0);
     const T mu = (T)ip.mu;
     const T zo = b.z[i], to = b.theta[i], ro = b.r[i];
     const T u = zo + to / mu;
@@ -382,8 +381,7 @@ __global__ __launch_bounds__(256) void k_init_r(IterBufs<T> b, IterParams ip, in
   const int seff = splits_in_use(b.ctl->count, ip.smax, ip.min_per);
   double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (i < n) {
-    double s = b.ctl->beta0;
-    for (int k = 0; k < seff; ++k) s += b.partial[(int64_t)k * n_pad + i];
+    const double s = sum_splits(b.partial, seff, n_pad, i, b.ctl->beta0);
     if (ip.fit & 1) b.z[i] = (T)((double)b.y[i] - s);
     b.r[i] = (T)(s + (double)b.z[i] - (double)b.y[i]);
     if (ip.fit & 2) b.theta[i] = (T)((ip.tau - ((double)b.z[i] < 0.0 ? 1.0 : 0.0)) / (double)n);

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -60,9 +61,27 @@ struct pqr_ctx {
   double state_mu = 0.0;
   std::vector<void*> allocs;
   std::vector<hipEvent_t> events;   // 2 per iteration of a chunk when profiling
+  // captured iteration chunk (launch_mode 0): its graph, the private capture stream
+  // and the key it was captured for
+  hipStream_t cap_s = nullptr;
+  hipGraph_t chunk_graph = nullptr;
+  hipGraphExec_t chunk_exec = nullptr;
+  int64_t chunk_len = 0;
+  int chunk_prec = -1;
+  IterParams chunk_ip{};
+  bool graph_failed = false;
   int batch_kp = 0;                 // capacity of the batched buffers (right-hand sides)
   BatchBufs bb{};
   float* btheta_best = nullptr;     // Kp x n_pad: per right-hand side, theta of its best dual
+  // batched launch variants chosen by the autotuner, per padded batch width Kp, with
+  // the mean kernel times (ms) of every candidate
+  struct TileChoice {
+    BatchTiles tiles;
+    bool bgemm_done = false, baxpy_done = false;
+    std::vector<double> bgemm_ms, baxpy_ms;
+    int64_t union_cols = 0;   // union of nonzero columns when the union product was timed
+  };
+  std::map<int, TileChoice> tiles;
   double* w_d = nullptr;            // p_pad penalty weights in FP64 (batched certificates)
   float* yb = nullptr;              // n_pad y in FP32 (batched iterations)
   float* feats = nullptr;           // p_pad x 4 features of the scoring network
@@ -236,6 +255,9 @@ extern "C" void pqr_destroy(pqr_ctx* ctx) {
   else (void)hipDeviceSynchronize();
   for (void* p : ctx->allocs) (void)hipFree(p);
   for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
+  if (ctx->chunk_exec) (void)hipGraphExecDestroy(ctx->chunk_exec);
+  if (ctx->chunk_graph) (void)hipGraphDestroy(ctx->chunk_graph);
+  if (ctx->cap_s) (void)hipStreamDestroy(ctx->cap_s);
   if (ctx->out_h) (void)hipHostFree(ctx->out_h);
   delete ctx;
 }
@@ -936,6 +958,51 @@ struct Run {
   }
 };
 
+bool same_params(const IterParams& a, const IterParams& b) {
+  return a.tau == b.tau && a.mu == b.mu && a.sigma == b.sigma && a.eta0 == b.eta0 && a.G == b.G &&
+         a.smax == b.smax && a.min_per == b.min_per && a.fit == b.fit;
+}
+
+// The graph of `chunk` iterations with parameters ip, captured once and reused while
+// they stay the same (the buffers of a context never move).  Captured on a private
+// stream of default priority; no memory-set nodes (the chunk is kernels only).
+// Returns false (and leaves the direct launches to the caller) when capture fails.
+template <typename T>
+bool chunk_graph(pqr_ctx* ctx, const IterBufs<T>& b, const IterParams& ip, int64_t chunk) {
+  if (ctx->graph_failed) return false;
+  const int prec = (int)sizeof(T);
+  if (ctx->chunk_exec && ctx->chunk_len == chunk && ctx->chunk_prec == prec &&
+      same_params(ctx->chunk_ip, ip))
+    return true;
+  if (ctx->chunk_exec) { (void)hipGraphExecDestroy(ctx->chunk_exec); ctx->chunk_exec = nullptr; }
+  if (ctx->chunk_graph) { (void)hipGraphDestroy(ctx->chunk_graph); ctx->chunk_graph = nullptr; }
+  bool ok = ctx->cap_s || hipStreamCreateWithFlags(&ctx->cap_s, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipStreamBeginCapture(ctx->cap_s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    hipError_t e = hipSuccess;
+    for (int64_t k = 0; k < chunk && e == hipSuccess; ++k)
+      e = launch_iteration<T>(ctx->g, b, ip, ctx->cap_s, nullptr, nullptr);
+    hipGraph_t gr = nullptr;
+    const hipError_t ee = hipStreamEndCapture(ctx->cap_s, &gr);
+    ok = e == hipSuccess && ee == hipSuccess && gr;
+    if (ok && hipGraphInstantiate(&ctx->chunk_exec, gr, nullptr, nullptr, 0) != hipSuccess) {
+      ctx->chunk_exec = nullptr;
+      ok = false;
+    }
+    if (ok) ctx->chunk_graph = gr;
+    else if (gr) (void)hipGraphDestroy(gr);
+  }
+  if (!ok) {
+    (void)hipGetLastError();
+    ctx->graph_failed = true;
+    return false;
+  }
+  ctx->chunk_len = chunk;
+  ctx->chunk_prec = prec;
+  ctx->chunk_ip = ip;
+  return true;
+}
+
 template <typename T>
 pqr_status solve_impl(pqr_ctx* ctx, const double* y, double tau, double lambda,
                       const double* weights, int start, const pqr_result* warm, pqr_result* out) {
@@ -951,9 +1018,14 @@ pqr_status solve_impl(pqr_ctx* ctx, const double* y, double tau, double lambda,
   while (run.active()) {
     const int64_t chunk = run.next_chunk();
     const IterBufs<T> b = bufs<T>(ctx);
-    for (int64_t k = 0; k < chunk; ++k)
-      HIPCHK(launch_iteration<T>(g, b, run.ip, s, prof ? ctx->events[2 * k] : nullptr,
-                                 prof ? ctx->events[2 * k + 1] : nullptr));
+    if (!prof && ctx->opt.launch_mode == 0 && chunk == ctx->opt.cert_every &&
+        chunk_graph<T>(ctx, b, run.ip, chunk)) {
+      HIPCHK(hipGraphLaunch(ctx->chunk_exec, s));
+    } else {
+      for (int64_t k = 0; k < chunk; ++k)
+        HIPCHK(launch_iteration<T>(g, b, run.ip, s, prof ? ctx->events[2 * k] : nullptr,
+                                   prof ? ctx->events[2 * k + 1] : nullptr));
+    }
     HIPCHK(hipStreamSynchronize(s));
     if (prof) {
       for (int64_t k = 0; k < chunk; ++k) {
@@ -1445,6 +1517,51 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
   for (int q = 0; q < ctx->G; ++q) eta[q] = (1.0 + ctx->opt.eta_margin) * mu * ctx->Lambda[q];
   for (int64_t q = 0; q < ng; ++q) ge[q] = (float)eta[ctx->gblock_h[q]];
   HIPCHK(hipMemcpyAsync((void*)b.geta, ge.data(), ng * 4, hipMemcpyHostToDevice, s));
+  // Autotuner, back-product: on the first batched solve of this width every launch
+  // variant runs once and is then timed over three launches on zero digits (the
+  // kernel's work does not depend on the values); the state is reset afterwards.
+  pqr_ctx::TileChoice& tc = ctx->tiles[Kp];
+  if (ctx->opt.tile_override > 0) {
+    const int o = ctx->opt.tile_override - 1;
+    if (o / 3 >= bgemm_variants() || o % 3 >= baxpy_variants()) {
+      ctx->err = "tile_override out of range";
+      return PQR_ERR_INVALID_ARG;
+    }
+    tc.tiles.bgemm = o / 3;
+    tc.tiles.baxpy = o % 3;
+    tc.bgemm_done = tc.baxpy_done = true;
+  }
+  auto time_launches = [&](auto&& launch, double* ms) -> pqr_status {
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    hipError_t e = launch();
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(e);
+    *ms = t / 3.0;
+    return PQR_OK;
+  };
+  if (!tc.bgemm_done) {
+    std::vector<int> all(Kp, 1);
+    HIPCHK(hipMemcpyAsync(const_cast<int*>(b.kact), all.data(), Kp * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(b.dig, 0, (size_t)3 * Kp * g.n_pad, s));
+    HIPCHK(launch_batch_zero(g, b, Kp, s));
+    tc.bgemm_ms.assign(bgemm_variants(), 0.0);
+    int best = 0;
+    for (int v = 0; v < bgemm_variants(); ++v) {
+      TRY(time_launches([&]() { return launch_bgemm_variant(g, b, Kp, v, s); }, &tc.bgemm_ms[v]));
+      if (tc.bgemm_ms[v] < tc.bgemm_ms[best]) best = v;
+    }
+    tc.tiles.bgemm = best;
+    tc.bgemm_done = true;
+  }
   HIPCHK(hipMemsetAsync(b.beta, 0, (size_t)Kp * g.p_pad * 4, s));
   HIPCHK(launch_batch_zero(g, b, Kp, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -1643,10 +1760,31 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
     TRY(push_masks());
     const int64_t chunk = std::min<int64_t>(ctx->opt.cert_every, ctx->opt.max_iter - it);
     for (int64_t q = 0; q < chunk; ++q)
-      HIPCHK(launch_batch_iteration(g, b, Kp, mu, sigma, eta[0], smax, min_per, s,
+      HIPCHK(launch_batch_iteration(g, b, Kp, mu, sigma, eta[0], smax, min_per, tc.tiles, s,
                                     prof ? ctx->events[2 * q] : nullptr,
                                     prof ? ctx->events[2 * q + 1] : nullptr));
     it += chunk;
+    int ucount = 0;
+    if (!tc.baxpy_done) {
+      HIPCHK(hipMemcpyAsync(&ucount, b.count, 4, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    if (!tc.baxpy_done && ucount >= 1024) {   // at least 16 matrix-core steps of union
+      // Autotuner, union product: between two iterations the union of nonzero
+      // columns and its digits are those of a live iterate, and the product's
+      // partials are rewritten by the next iteration before they are read, so the
+      // variants (equal results: exact integer sums) are timed on the real union.
+      tc.baxpy_ms.assign(baxpy_variants(), 0.0);
+      int best = 0;
+      for (int v = 0; v < baxpy_variants(); ++v) {
+        TRY(time_launches([&]() { return launch_baxpy_variant(g, b, Kp, smax, min_per, v, s); },
+                          &tc.baxpy_ms[v]));
+        if (tc.baxpy_ms[v] < tc.baxpy_ms[best]) best = v;
+      }
+      tc.tiles.baxpy = best;
+      tc.baxpy_done = true;
+      tc.union_cols = ucount;
+    }
     HIPCHK(hipStreamSynchronize(s));
     if (prof) {
       for (int64_t q = 0; q < chunk; ++q) {
@@ -1728,6 +1866,26 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
 }
 
 }  // namespace
+
+extern "C" pqr_status pqr_batch_tiles(pqr_ctx* ctx, int K, int* bgemm_variant, int* baxpy_variant,
+                                      double* bgemm_ms, double* baxpy_ms, int64_t* union_cols) {
+  if (!ctx || K < 1 || K > 128) return PQR_ERR_INVALID_ARG;
+  const int Kp = (K + 15) / 16 * 16;
+  auto it = ctx->tiles.find(Kp);
+  if (it == ctx->tiles.end() || !it->second.bgemm_done) {
+    ctx->err = "no batched solve of this width has run on the context";
+    return PQR_ERR_INVALID_ARG;
+  }
+  const pqr_ctx::TileChoice& tc = it->second;
+  if (bgemm_variant) *bgemm_variant = tc.tiles.bgemm;
+  if (baxpy_variant) *baxpy_variant = tc.baxpy_done ? tc.tiles.baxpy : -1;
+  if (union_cols) *union_cols = tc.union_cols;
+  for (int v = 0; v < 3; ++v) {
+    if (bgemm_ms) bgemm_ms[v] = v < (int)tc.bgemm_ms.size() ? tc.bgemm_ms[v] : 0.0;
+    if (baxpy_ms) baxpy_ms[v] = v < (int)tc.baxpy_ms.size() ? tc.baxpy_ms[v] : 0.0;
+  }
+  return PQR_OK;
+}
 
 extern "C" pqr_status pqr_solve_batch(pqr_ctx* ctx, const double* y, int K, const double* taus,
                                       const double* lambdas, const double* weights,
@@ -1844,63 +2002,33 @@ extern "C" pqr_status pqr_mlp_adam(float* params, const float* grad, float* m, f
   return PQR_OK;
 }
 
-extern "C" pqr_status pqr_solve_learned(pqr_ctx* ctx, const double* y, double tau, double lambda,
-                                        const double* weights, const float* mlp_params,
-                                        double threshold, int max_rounds, pqr_result* out,
-                                        pqr_learned_report* rep) {
-  if (!ctx) return PQR_ERR_INVALID_ARG;
-  const auto t0 = std::chrono::steady_clock::now();
+namespace {
+
+// The active-set rounds shared by the learned and the screened warm starts: the
+// problem restricted to A is solved by FS-QRPPA from bw (the full-length starting
+// coefficients on the solver scale; z and theta derived from them on the device),
+// the FP64 certificate on the full design judges the result, columns outside A
+// whose |x~_j^T theta'| exceeds lambda_j (1 + 1e-6) join A, and if no round
+// passes the plain zero-start solve on the full design gives the answer.
+pqr_status active_set_rounds(pqr_ctx* ctx, const double* y, double tau, double lambda,
+                             const double* weights, std::vector<int64_t> A,
+                             std::vector<double> bw, double lmax, int max_rounds,
+                             std::chrono::steady_clock::time_point t0, pqr_result* out,
+                             pqr_learned_report& r) {
   auto secs = [&]() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   };
-  TRY(validate_problem(ctx, y, tau, lambda, weights));
-  if (!mlp_params || max_rounds < 1) {
-    ctx->err = "pqr_solve_learned needs the network parameters and max_rounds >= 1";
-    return PQR_ERR_INVALID_ARG;
-  }
   const Geom& g = ctx->g;
   hipStream_t s = ctx->s;
-  pqr_learned_report r{};
-  // 1. proposal: features, network, thresholded active set
-  if (!ctx->feats) TRY(dalloc(ctx, &ctx->feats, g.p_pad * 16));
-  if (!ctx->mlp_out) TRY(dalloc(ctx, &ctx->mlp_out, g.p_pad * 8));
-  double lmax = 0.0;
-  TRY(pqr_features(ctx, y, tau, lambda, weights, ctx->feats, &lmax));
-  const double q = ctx->out_h[0];   // tau-quantile of y (null-fit intercept)
-  HIPCHK(launch_mlp_forward(mlp_params, ctx->feats, g.p, ctx->mlp_out, s));
-  std::vector<float> o(g.p * 2);
-  HIPCHK(hipMemcpyAsync(o.data(), ctx->mlp_out, g.p * 8, hipMemcpyDeviceToHost, s));
   std::vector<double> cinv(g.p);
   HIPCHK(hipMemcpyAsync(cinv.data(), ctx->cinv_d, g.p * 8, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  double my = 0, vy = 0;
-  for (int64_t i = 0; i < g.n; ++i) my += y[i];
-  my /= g.n;
-  for (int64_t i = 0; i < g.n; ++i) vy += (y[i] - my) * (y[i] - my);
-  const double sdy = std::sqrt(vy / g.n);
-  // A = {j : o1_j > threshold} plus the 32 columns with the largest logits, so
-  // that a cautious network still proposes a starting support
-  std::vector<int64_t> order;
-  for (int64_t j = 0; j < g.p; ++j)
-    if (cinv[j] != 0.0) order.push_back(j);
-  const size_t ktop = std::min<size_t>(32, order.size());
-  std::partial_sort(order.begin(), order.begin() + ktop, order.end(),
-                    [&](int64_t a, int64_t b) { return o[2 * a + 1] > o[2 * b + 1]; });
-  std::vector<char> pick(g.p, 0);
-  for (size_t k = 0; k < ktop; ++k) pick[order[k]] = 1;
-  std::vector<int64_t> A;
-  for (int64_t j = 0; j < g.p; ++j)
-    if (cinv[j] != 0.0 && (pick[j] || o[2 * j + 1] > threshold)) A.push_back(j);
-  r.active_initial = (int64_t)A.size();
-  r.seconds_proposal = secs();
   std::vector<double> bfull(g.p + 1, 0.0), zbest(g.n), tbest(g.n);
   std::vector<double> lamj(g.p);
   for (int64_t j = 0; j < g.p; ++j) lamj[j] = lambda * (weights ? weights[1 + j] : 1.0);
   // warm state carried between rounds (full-length beta on the solver scale); the
   // first round derives z = y - X~beta^0 and theta from its signs on the device
-  std::vector<double> bw(g.p + 1, 0.0), zw(g.n), tw(g.n);
-  bw[0] = q;
-  for (int64_t j : A) bw[1 + j] = o[2 * j] * sdy;
+  std::vector<double> zw(g.n), tw(g.n);
   bool ok = false;
   double cert[4] = {0, 0, 0, 0};
   int64_t iters = 0;
@@ -2014,6 +2142,128 @@ extern "C" pqr_status pqr_solve_learned(pqr_ctx* ctx, const double* y, double ta
     out->seconds = secs();
   }
   r.seconds_check = secs();
-  if (rep) *rep = r;
   return status;
+}
+
+}  // namespace
+
+extern "C" pqr_status pqr_solve_learned(pqr_ctx* ctx, const double* y, double tau, double lambda,
+                                        const double* weights, const float* mlp_params,
+                                        double threshold, int max_rounds, pqr_result* out,
+                                        pqr_learned_report* rep) {
+  if (!ctx) return PQR_ERR_INVALID_ARG;
+  const auto t0 = std::chrono::steady_clock::now();
+  auto secs = [&]() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  };
+  TRY(validate_problem(ctx, y, tau, lambda, weights));
+  if (!mlp_params || max_rounds < 1) {
+    ctx->err = "pqr_solve_learned needs the network parameters and max_rounds >= 1";
+    return PQR_ERR_INVALID_ARG;
+  }
+  const Geom& g = ctx->g;
+  hipStream_t s = ctx->s;
+  pqr_learned_report r{};
+  // 1. proposal: features, network, thresholded active set
+  if (!ctx->feats) TRY(dalloc(ctx, &ctx->feats, g.p_pad * 16));
+  if (!ctx->mlp_out) TRY(dalloc(ctx, &ctx->mlp_out, g.p_pad * 8));
+  double lmax = 0.0;
+  TRY(pqr_features(ctx, y, tau, lambda, weights, ctx->feats, &lmax));
+  const double q = ctx->out_h[0];   // tau-quantile of y (null-fit intercept)
+  HIPCHK(launch_mlp_forward(mlp_params, ctx->feats, g.p, ctx->mlp_out, s));
+  std::vector<float> o(g.p * 2);
+  HIPCHK(hipMemcpyAsync(o.data(), ctx->mlp_out, g.p * 8, hipMemcpyDeviceToHost, s));
+  std::vector<double> cinv(g.p);
+  HIPCHK(hipMemcpyAsync(cinv.data(), ctx->cinv_d, g.p * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double my = 0, vy = 0;
+  for (int64_t i = 0; i < g.n; ++i) my += y[i];
+  my /= g.n;
+  for (int64_t i = 0; i < g.n; ++i) vy += (y[i] - my) * (y[i] - my);
+  const double sdy = std::sqrt(vy / g.n);
+  // A = {j : o1_j > threshold} plus the 32 columns with the largest logits, so
+  // that a cautious network still proposes a starting support
+  std::vector<int64_t> order;
+  for (int64_t j = 0; j < g.p; ++j)
+    if (cinv[j] != 0.0) order.push_back(j);
+  const size_t ktop = std::min<size_t>(32, order.size());
+  std::partial_sort(order.begin(), order.begin() + ktop, order.end(),
+                    [&](int64_t a, int64_t b) { return o[2 * a + 1] > o[2 * b + 1]; });
+  std::vector<char> pick(g.p, 0);
+  for (size_t k = 0; k < ktop; ++k) pick[order[k]] = 1;
+  std::vector<int64_t> A;
+  for (int64_t j = 0; j < g.p; ++j)
+    if (cinv[j] != 0.0 && (pick[j] || o[2 * j + 1] > threshold)) A.push_back(j);
+  r.active_initial = (int64_t)A.size();
+  r.seconds_proposal = secs();
+  std::vector<double> bw(g.p + 1, 0.0);
+  bw[0] = q;
+  for (int64_t j : A) bw[1 + j] = o[2 * j] * sdy;
+  const pqr_status st = active_set_rounds(ctx, y, tau, lambda, weights, std::move(A),
+                                          std::move(bw), lmax, max_rounds, t0, out, r);
+  if (rep) *rep = r;
+  return st;
+}
+
+// Screened warm start: the sequential strong rule proposes A from the null-fit
+// scores S_j = x~_j^T psi / n (psi the null dual at the tau-quantile):
+// A = {j : |S_j| >= (2 lambda - lambda_prev) w_j}, lambda_prev = lambda_max unless
+// given (budget 0), or the `budget` columns with the largest |S_j| / w_j; zero
+// weights always join A.  The active-set rounds of the learned warm start then make
+// the answer exact: the full-design certificate decides and violators join A.
+extern "C" pqr_status pqr_solve_screened(pqr_ctx* ctx, const double* y, double tau, double lambda,
+                                         const double* weights, double lambda_prev,
+                                         int64_t budget, int max_rounds, pqr_result* out,
+                                         pqr_learned_report* rep) {
+  if (!ctx) return PQR_ERR_INVALID_ARG;
+  const auto t0 = std::chrono::steady_clock::now();
+  TRY(validate_problem(ctx, y, tau, lambda, weights));
+  if (max_rounds < 1 || budget < 0 || !(lambda_prev >= 0) || !std::isfinite(lambda_prev)) {
+    ctx->err = "pqr_solve_screened needs max_rounds >= 1, budget >= 0 and a finite lambda_prev >= 0";
+    return PQR_ERR_INVALID_ARG;
+  }
+  const Geom& g = ctx->g;
+  hipStream_t s = ctx->s;
+  pqr_learned_report r{};
+  std::vector<double> score(g.p), cinv(g.p);
+  double lmax = 0.0;
+  TRY(pqr_lambda_max(ctx, y, tau, weights, &lmax, score.data()));
+  const double q = ctx->out_h[0];   // tau-quantile of y (null-fit intercept)
+  HIPCHK(hipMemcpyAsync(cinv.data(), ctx->cinv_d, g.p * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  auto w = [&](int64_t j) { return weights ? weights[1 + j] : 1.0; };
+  std::vector<int64_t> cand;   // penalized, non-excluded columns
+  std::vector<int64_t> A;
+  for (int64_t j = 0; j < g.p; ++j) {
+    if (cinv[j] == 0.0) continue;
+    if (w(j) == 0.0) A.push_back(j);
+    else cand.push_back(j);
+  }
+  auto ratio = [&](int64_t j) { return std::fabs(score[j]) / w(j); };
+  if (budget > 0) {
+    const size_t k = std::min<size_t>((size_t)budget, cand.size());
+    std::partial_sort(cand.begin(), cand.begin() + k, cand.end(),
+                      [&](int64_t a, int64_t b) { return ratio(a) > ratio(b); });
+    A.insert(A.end(), cand.begin(), cand.begin() + k);
+  } else {
+    const double cut = 2.0 * lambda - (lambda_prev > 0 ? lambda_prev : lmax);
+    size_t kept = 0;
+    for (int64_t j : cand)
+      if (ratio(j) >= cut) { A.push_back(j); ++kept; }
+    if (kept == 0) {   // every column screened out: start from the 32 best scores
+      const size_t k = std::min<size_t>(32, cand.size());
+      std::partial_sort(cand.begin(), cand.begin() + k, cand.end(),
+                        [&](int64_t a, int64_t b) { return ratio(a) > ratio(b); });
+      A.insert(A.end(), cand.begin(), cand.begin() + k);
+    }
+  }
+  std::sort(A.begin(), A.end());
+  r.active_initial = (int64_t)A.size();
+  r.seconds_proposal = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  std::vector<double> bw(g.p + 1, 0.0);
+  bw[0] = q;
+  const pqr_status st = active_set_rounds(ctx, y, tau, lambda, weights, std::move(A),
+                                          std::move(bw), lmax, max_rounds, t0, out, r);
+  if (rep) *rep = r;
+  return st;
 }

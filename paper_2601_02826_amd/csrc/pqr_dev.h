@@ -32,6 +32,23 @@ template <> struct Vec4<double> { using type = double4; };
 // row offset `row0` inside a segment.  The split lets a wavefront issue the loads of several columns before
 // it decodes any of them (more bytes in flight per wavefront).
 // ---------------------------------------------------------------------------
+// s + sum_k p[k n_pad + i] over the splits k = 0 .. seff-1, added in that order
+// (deterministic) with eight loads in flight: the split partials of one row are
+// n_pad apart, and a row's sum is one thread's work.
+__device__ __forceinline__ double sum_splits(const double* __restrict__ p, int seff,
+                                             int64_t n_pad, int64_t i, double s) {
+  int k = 0;
+  for (; k + 8 <= seff; k += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(k + u) * n_pad + i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; k < seff; ++k) s += p[(int64_t)k * n_pad + i];
+  return s;
+}
+
 __device__ __forceinline__ float ubyte(uint32_t w, int b) { return (float)((w >> (8 * b)) & 0xffu); }
 
 template <int FMT, int RPL> struct Raw;

@@ -216,11 +216,24 @@ struct BatchBufs {
   double* bscale;       // Kp coefficient digit scale d_k (power of two)
   const int* kact;      // Kp: 1 = iterate right-hand side k, 0 = frozen (certified or padding)
 };
+// Launch variants of the two matrix-core kernels of a batched iteration (chosen
+// per batch width by the solver's autotuner): back-product (k_bgemm) and union
+// product (k_baxpy); variant 0 is the default of each.
+struct BatchTiles {
+  int bgemm = 0, baxpy = 0;
+};
+int bgemm_variants();
+int baxpy_variants();
+hipError_t launch_bgemm_variant(const Geom& g, const BatchBufs& b, int Kp, int v, hipStream_t s,
+                                hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+hipError_t launch_baxpy_variant(const Geom& g, const BatchBufs& b, int Kp, int smax, int min_per,
+                                int v, hipStream_t s);
 // One batched iteration; with non-null events, ev0/ev1 are recorded around the
 // back-product kernel (k_bgemm).
 hipError_t launch_batch_iteration(const Geom& g, const BatchBufs& b, int Kp, double mu,
                                   double sigma, double eta0, int smax, int min_per,
-                                  hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                                  const BatchTiles& tiles, hipStream_t s, hipEvent_t ev0 = nullptr,
+                                  hipEvent_t ev1 = nullptr);
 hipError_t launch_batch_zero(const Geom& g, const BatchBufs& b, int Kp, hipStream_t s);
 
 // Exact-integer certificate of batched right-hand sides.  theta_q,k = unit_k T_k

@@ -99,3 +99,38 @@ def test_batch_rejects_sizes_beyond_exact_integer_range():
         ctx.solve_batch(y, [0.5], [0.1])
     assert e.value.status == pq.PQR_ERR_UNSUPPORTED and "2^31" in str(e.value)
     ctx.close()
+
+
+@pytest.mark.parametrize("K", [21, 128])
+def test_every_launch_variant_gives_identical_iterates(K):
+    """The autotuner picks among launch variants of the back-product and the union
+    product; each computes the same exact integer sums, so 300 iterations under every
+    forced combination equal the default bit for bit, and the tuner's own choice (and
+    the candidate times it measured) are reported."""
+    n, p, G = 1500, 700, 3
+    X, y = H.genotype_problem(n, p, seed=31)
+    X1, _, _ = H.oracle_design(X, True)
+    taus = np.resize(np.array([0.2, 0.5, 0.8]), K)
+    fr = np.resize(np.array([0.9, 0.6, 0.4, 0.3, 0.25, 0.2, 0.5, 0.7]), K)
+    lams = np.array([f * pqr.lambda_max(X1, y, t) for f, t in zip(fr, taus)])
+    ref = None
+    for o in range(1, 10):
+        ctx = _ctx(X, G=G, tol_gap=1e-12, cert_every=100, max_iter=300, tile_override=o)
+        res = ctx.solve_batch(y, taus, lams, allow_not_converged=True)
+        B = np.stack([r["beta_std"] for r in res])
+        Th = np.stack([r["theta"] for r in res])
+        if ref is None:
+            ref = (B, Th)
+        else:
+            assert np.array_equal(B, ref[0]) and np.array_equal(Th, ref[1]), o
+        ctx.close()
+    ctx = _ctx(X, G=G, tol_gap=1e-12, cert_every=100, max_iter=300)
+    res = ctx.solve_batch(y, taus, lams, allow_not_converged=True)
+    assert np.array_equal(np.stack([r["beta_std"] for r in res]), ref[0])
+    t = ctx.batch_tiles(K)
+    print(f"K={K}: tuner chose back-product {t['bgemm_variant']} {t['bgemm_ms']}, union product "
+          f"{t['baxpy_variant']} {t['baxpy_ms']}")
+    assert 0 <= t["bgemm_variant"] < 3 and t["bgemm_ms"][t["bgemm_variant"]] == min(t["bgemm_ms"])
+    # the union product is timed once its union holds 1024 columns (never at p = 700)
+    assert t["baxpy_variant"] == -1 and t["union_cols"] == 0
+    ctx.close()

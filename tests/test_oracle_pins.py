@@ -628,3 +628,31 @@ def test_uniqueness_check_against_highs_face_ranges():
     (a, b), = lp.highs_face_range(X1, y, tau, lam2, val2, [0], rel=1e-12)
     lo_q, hi_q = pqr.quantile_minimizers(y, tau)
     assert a == pytest.approx(lo_q, abs=1e-7) and b == pytest.approx(hi_q, abs=1e-7)
+
+
+@pytest.mark.parametrize("seed,tau,frac", [(51, 0.5, 0.5), (52, 0.3, 0.3), (53, 0.8, 0.2)])
+def test_strong_rule_screened_solve_reaches_the_optimum(seed, tau, frac):
+    """The strong rule is a heuristic (it may discard an active column); the dual check
+    over every discarded column (Prop. 1 at the restricted optimum) makes the screened
+    solve exact: its value equals the full LP optimum and its coefficients vanish
+    outside the final set.  At lambda >= lambda_max the rule keeps nothing and the null
+    fit is already optimal."""
+    rng = np.random.default_rng(seed)
+    n, p = 80, 300
+    X = rng.integers(0, 3, (n, p)).astype(float)
+    X1 = pqr.with_intercept(pqr.standardize(X)[0])
+    y = X1[:, 1:6] @ rng.uniform(0.5, 1.5, 5) + rng.standard_t(3, n)
+    lmax = pqr.lambda_max(X1, y, tau)
+    _, psi = pqr.null_dual(y, tau)
+    score = X1[:, 1:].T @ psi / n
+    assert np.max(np.abs(score)) == pytest.approx(lmax, rel=1e-12)
+    assert len(pqr.strong_rule(score, 1.0 * lmax, lmax)) == 1     # only the maximiser
+    assert len(pqr.strong_rule(score, 1.2 * lmax, lmax)) == 0
+    lam = np.full(p + 1, frac * lmax)
+    lam[0] = 0.0
+    A = pqr.strong_rule(score, frac * lmax, lmax)
+    val, beta, th, rounds, added = pqr.screened_solve(X1, y, tau, lam, A, lp.highs_with_duals)
+    full, _ = lp.highs(X1, y, tau, lam)
+    assert val == pytest.approx(full, rel=1e-9, abs=1e-12)
+    assert pqr.objective(X1, y, beta, tau, lam) == pytest.approx(full, rel=1e-8)
+    assert np.max(np.abs(X1[:, 1:].T @ th) / lam[1:]) <= 1 + 1e-8
