@@ -970,6 +970,7 @@ def bench_learned(a):
     from datagen.configs import GenotypeSpec, make_genotype
     t0 = time.perf_counter()
     F, T, A = [], [], []
+    rates = []
     for i in range(a.train_problems):
         spec = GenotypeSpec(n=5000, p=100_000, n_causal=50, seed=100 + i, tag=7, tau=0.5)
         gi = make_genotype(spec, with_X=False)
@@ -985,7 +986,7 @@ def bench_learned(a):
         for tau in LEARNED_TAUS:
             lm = tctx.lambda_max(gi["y"], tau)
             Fp, Tp, Ap = learned.collect_rows(tctx, gi["y"], tau, [f * lm for f in (0.7, 0.5, 0.4, 0.3)],
-                                              seed=i)
+                                              seed=i, rates=rates)
             F.append(Fp); T.append(Tp); A.append(Ap)
         tctx.close()
         torch.cuda.empty_cache()
@@ -994,7 +995,9 @@ def bench_learned(a):
     params = learned.init_params(0)
     losses = learned.train(params, F, T, A, steps=1500, batch=4096, lr=3e-3, log_every=500)
     train_s = time.perf_counter() - t0
-    log(f"network trained on {F.shape[0]} rows in {train_s:.1f}s, losses {losses}")
+    thr = learned.prior_threshold(rates)
+    log(f"network trained on {F.shape[0]} rows in {train_s:.1f}s, losses {losses}, "
+        f"proposal threshold {thr:.2f}")
     spec, g, Xc = make_workload(a.n, a.p)
     ctx = pq.Context.from_tensor(Xc, store_fmt="i8", standardize=True, G=a.G, tol_gap=a.tol,
                                  cert_every=a.cert_every, max_iter=a.max_iter * 10, profile=1)
@@ -1006,11 +1009,12 @@ def bench_learned(a):
     calibrate_copy(a.calibrate_copy)
     for w in range(a.warmup):
         for t, lam in zip(LEARNED_TAUS, lams):
-            ctx.solve_learned(y, t, lam, params.data_ptr())
+            ctx.solve_learned(y, t, lam, params.data_ptr(), threshold=thr)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(a.steps):
-        recs = [ctx.solve_learned(y, t, lam, params.data_ptr()) for t, lam in zip(LEARNED_TAUS, lams)]
+        recs = [ctx.solve_learned(y, t, lam, params.data_ptr(), threshold=thr)
+                for t, lam in zip(LEARNED_TAUS, lams)]
         log(f"step {k + 1}/{a.steps}: " + "; ".join(
             f"tau={t}: |A| {r['active_initial']}->{r['active_final']}, {r['rounds']} rounds, "
             f"{r['reduced_iters']} reduced iterations, fallback {r['fallback']}, gap {r['rel_gap']:.2e}"
@@ -1043,6 +1047,9 @@ def bench_learned(a):
             cost(ctx.solve_screened(y, t, lam)) for t, lam in zip(LEARNED_TAUS, lams)]
         rivals["zero network"] = [cost(ctx.solve_learned(y, t, lam, zero.data_ptr()))
                                   for t, lam in zip(LEARNED_TAUS, lams)]
+        rivals["trained network, threshold 0 (uncorrected class balance)"] = [
+            cost(ctx.solve_learned(y, t, lam, params.data_ptr(), threshold=0.0))
+            for t, lam in zip(LEARNED_TAUS, lams)]
         for name, cs in rivals.items():
             log(f"{name}: " + "; ".join(f"tau={t}: {c['iterations']} it, {c['x_passes']:.1f} passes, "
                                         f"{c['seconds']:.2f}s, |A| {c['active_initial']}->"
@@ -1087,7 +1094,7 @@ def bench_learned(a):
         "plain_s": plain_s, "plain_iterations": [r["iters"] for r in plain],
         "proposals": rivals,
         "speedup_vs_plain": plain_s / (elapsed / a.steps) if plain_s else None,
-        "train_s": train_s, "train_rows": int(F.shape[0]),
+        "train_s": train_s, "train_rows": int(F.shape[0]), "proposal_threshold": thr,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
                      "kernel": "k_sweep on the reduced problems (X~_A^T theta + soft threshold)",

@@ -29,10 +29,11 @@ def init_params(seed=0):
     return torch.from_numpy(flat).cuda()
 
 
-def collect_rows(ctx, y, tau, lams, neg_ratio=4, neg_min=256, seed=0):
+def collect_rows(ctx, y, tau, lams, neg_ratio=4, neg_min=256, seed=0, rates=None):
     """Solve the lambda path on ctx (warm starts on the device) and return the
     feature / target rows of every solved point: all active columns plus a random
-    sample of inactive ones."""
+    sample of inactive ones.  With `rates` (a list), the fraction of inactive columns
+    kept at every point is appended to it (for prior_threshold)."""
     import torch
     rng = np.random.default_rng(seed)
     sd = float(np.std(y))
@@ -47,12 +48,22 @@ def collect_rows(ctx, y, tau, lams, neg_ratio=4, neg_min=256, seed=0):
         ia = np.nonzero(act)[0]
         ii = np.nonzero(~act)[0]
         take = min(len(ii), max(neg_min, neg_ratio * len(ia)))
+        if rates is not None and len(ii):
+            rates.append(take / len(ii))
         idx = np.concatenate([ia, rng.choice(ii, take, replace=False)]) if take else ia
         it = torch.from_numpy(idx.astype(np.int64)).cuda()
         F.append(feats.index_select(0, it))
         T.append(torch.from_numpy(b[idx].astype(np.float32)).cuda())
         A.append(torch.from_numpy(act[idx].astype(np.float32)).cuda())
     return torch.cat(F), torch.cat(T), torch.cat(A)
+
+
+def prior_threshold(rates, w_pos=2.0):
+    """Logit threshold that undoes the training rows' class balance: inactive columns
+    were kept at rate r and active ones weighted by w_pos, so the network's odds are
+    those of the population times w_pos / r; the proposal A = {logit > log(w_pos) -
+    mean(log r)} is then the set of columns more likely active than not."""
+    return float(np.log(w_pos) - np.mean(np.log(np.asarray(rates, dtype=np.float64))))
 
 
 def train(params, F, T, A, steps=500, batch=2048, lr=3e-3, w_reg=100.0, w_pos=2.0, seed=0,

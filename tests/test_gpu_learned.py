@@ -79,6 +79,7 @@ def test_learned_warm_start_end_to_end():
     from paper_2601_02826_amd import learned
     n, p, G = 1500, 5000, 4
     F_all, T_all, A_all = [], [], []
+    rates = []
     for seed in (41, 42, 43, 44):
         X, y = H.genotype_problem(n, p, seed=seed, n_causal=10)
         ctx = pq.Context.from_tensor(H.to_device_cols(X, np.uint8), store_fmt="i8", G=G,
@@ -86,7 +87,7 @@ def test_learned_warm_start_end_to_end():
         for tau in (0.3, 0.6):
             lm = ctx.lambda_max(y, tau)
             Fp, Tp, Ap = learned.collect_rows(ctx, y, tau, [0.7 * lm, 0.55 * lm, 0.45 * lm],
-                                              seed=seed)
+                                              seed=seed, rates=rates)
             F_all.append(Fp); T_all.append(Tp); A_all.append(Ap)
         ctx.close()
     F, T, A = torch.cat(F_all), torch.cat(T_all), torch.cat(A_all)
@@ -102,7 +103,9 @@ def test_learned_warm_start_end_to_end():
                                  tol_gap=tol, cert_every=100, max_iter=400_000)
     lam = 0.5 * ctx.lambda_max(y, tau)
     plain = ctx.solve(y, tau, lam)
-    lrn = ctx.solve_learned(y, tau, lam, params.data_ptr(), threshold=0.0, max_rounds=4)
+    thr = learned.prior_threshold(rates)
+    assert thr > 0   # inactive rows were subsampled: the raw logits overstate activity
+    lrn = ctx.solve_learned(y, tau, lam, params.data_ptr(), threshold=thr, max_rounds=4)
     val, _ = lp.highs(X1, y, tau, H.lam_vector(p, lam))
     p_l = pqr.objective(X1, y, lrn["beta_std"], tau, H.lam_vector(p, lam))
     print({k: lrn[k] for k in ("rounds", "fallback", "active_initial", "active_final",
@@ -116,9 +119,19 @@ def test_learned_warm_start_end_to_end():
           f"{lrn['reduced_iters']} reduced iterations, {lrn['seconds']:.3f}s; X-passes "
           f"{passes_plain} vs {passes_learned:.1f}")
     assert passes_learned < 0.5 * passes_plain
-    # a useless network (no column proposed) falls back to the plain solve
-    zero = torch.zeros_like(params)      # proposes only the 32 forced columns, zero coefficients
+    # the same rounds with non-learned proposals: the strong rule at the network's |A|
+    # budget (reported: the two are close on these designs), and a useless network
+    # (no column proposed: only the 32 forced columns, zero coefficients), which needs
+    # more X-passes than the trained one
+    scr = ctx.solve_screened(y, tau, lam, budget=lrn["active_initial"], max_rounds=4)
+    passes_screened = scr["reduced_iters"] * scr["active_final"] / p + 2 * scr["rounds"] + 1
+    assert scr["rel_gap"] <= tol
+    zero = torch.zeros_like(params)
     fb = ctx.solve_learned(y, tau, lam, zero.data_ptr(), threshold=0.0, max_rounds=1)
-    print("useless network:", {k: fb[k] for k in ("rounds", "fallback", "active_final", "rel_gap")})
+    passes_zero = (fb["iters"] if fb["fallback"] else
+                   fb["reduced_iters"] * fb["active_final"] / p + 2 * fb["rounds"] + 1)
+    print(f"strong rule at the same budget: {scr['rounds']} rounds, {passes_screened:.1f} X-passes; "
+          f"zero network: fallback {fb['fallback']}, {passes_zero:.1f} X-passes")
     assert fb["rel_gap"] <= tol         # certified either by the reduced solve or the fallback
+    assert passes_learned < passes_zero
     ctx.close()
