@@ -958,6 +958,7 @@ def bench_sim(a):
 
 LEARNED_TAUS = (0.1, 0.5, 0.9)
 LEARNED_FRAC = 0.4
+LEARNED_ROUNDS = 8
 
 
 def bench_learned(a):
@@ -1009,11 +1010,12 @@ def bench_learned(a):
     calibrate_copy(a.calibrate_copy)
     for w in range(a.warmup):
         for t, lam in zip(LEARNED_TAUS, lams):
-            ctx.solve_learned(y, t, lam, params.data_ptr(), threshold=thr)
+            ctx.solve_learned(y, t, lam, params.data_ptr(), threshold=thr, max_rounds=LEARNED_ROUNDS)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(a.steps):
-        recs = [ctx.solve_learned(y, t, lam, params.data_ptr(), threshold=thr)
+        recs = [ctx.solve_learned(y, t, lam, params.data_ptr(), threshold=thr,
+                                  max_rounds=LEARNED_ROUNDS)
                 for t, lam in zip(LEARNED_TAUS, lams)]
         log(f"step {k + 1}/{a.steps}: " + "; ".join(
             f"tau={t}: |A| {r['active_initial']}->{r['active_final']}, {r['rounds']} rounds, "
@@ -1037,28 +1039,31 @@ def bench_learned(a):
 
     # the same active-set rounds with non-learned proposals: the sequential strong rule
     # at the network's |A| budget and on its own, and the network with zero parameters
+    # (the basic strong rule 2 lambda - lambda_max keeps every column below lambda_max / 2,
+    # so at 0.4 lambda_max it is the full problem and is not run)
     zero = torch.zeros_like(params)
     rivals = {"trained network": [cost(r) for r in recs]}
-    if not a.skip_reference:
-        rivals["strong rule, network's |A| budget"] = [
-            cost(ctx.solve_screened(y, t, lam, budget=r["active_initial"]))
-            for t, lam, r in zip(LEARNED_TAUS, lams, recs)]
-        rivals["strong rule (2 lambda - lambda_max)"] = [
-            cost(ctx.solve_screened(y, t, lam)) for t, lam in zip(LEARNED_TAUS, lams)]
-        rivals["zero network"] = [cost(ctx.solve_learned(y, t, lam, zero.data_ptr()))
-                                  for t, lam in zip(LEARNED_TAUS, lams)]
-        rivals["trained network, threshold 0 (uncorrected class balance)"] = [
-            cost(ctx.solve_learned(y, t, lam, params.data_ptr(), threshold=0.0))
-            for t, lam in zip(LEARNED_TAUS, lams)]
-        for name, cs in rivals.items():
-            log(f"{name}: " + "; ".join(f"tau={t}: {c['iterations']} it, {c['x_passes']:.1f} passes, "
-                                        f"{c['seconds']:.2f}s, |A| {c['active_initial']}->"
-                                        f"{c['active_final']}, fallback {c['fallback']}"
-                                        for t, c in zip(LEARNED_TAUS, cs)))
+    runs = [("strong rule, network's |A| budget",
+             lambda t, lam, r: ctx.solve_screened(y, t, lam, budget=r["active_initial"],
+                                                  max_rounds=LEARNED_ROUNDS)),
+            ("zero network",
+             lambda t, lam, r: ctx.solve_learned(y, t, lam, zero.data_ptr(), max_rounds=LEARNED_ROUNDS)),
+            ("trained network, threshold 0 (uncorrected class balance)",
+             lambda t, lam, r: ctx.solve_learned(y, t, lam, params.data_ptr(), threshold=0.0,
+                                                 max_rounds=LEARNED_ROUNDS))]
+    for name, fn in ([] if a.skip_reference else runs):
+        rivals[name] = []
+        for t, lam, r in zip(LEARNED_TAUS, lams, recs):
+            c = cost(fn(t, lam, r))
+            rivals[name].append(c)
+            log(f"{name}: tau={t}: {c['iterations']} it, {c['x_passes']:.1f} passes, "
+                f"{c['seconds']:.2f}s, |A| {c['active_initial']}->{c['active_final']}, "
+                f"fallback {c['fallback']}")
     plain = []
     if not a.skip_reference:
         for t, lam in zip(LEARNED_TAUS, lams):
             plain.append(ctx.solve(y, t, lam, allow_not_converged=True))
+            log(f"plain zero start tau={t}: {plain[-1]['iters']} iterations, {plain[-1]['seconds']:.1f}s")
     plain_s = sum(r["seconds"] for r in plain) if plain else None
     sw_ms = sum(r["reduced_sweep_ms"] for r in recs)
     sw_bytes = sum(r["reduced_sweep_bytes"] for r in recs)

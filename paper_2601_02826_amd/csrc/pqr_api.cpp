@@ -13,6 +13,7 @@
 
 #include "../../include/pqr.h"
 #include "pqr_kernels.h"
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 using namespace pqr;
 
@@ -107,6 +108,14 @@ struct pqr_ctx {
 };
 
 namespace {
+
+// A roctx range around an entry point (visible with rocprofv3 --marker-trace).
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 #define HIPCHK(expr)                                                              \
   do {                                                                            \
@@ -464,6 +473,7 @@ static pqr_status create_rest(pqr_ctx* ctx) {
 }
 
 extern "C" pqr_status pqr_create(pqr_ctx** out, const pqr_design* X, const pqr_options* opt) {
+  Range range_("pqr_create");
   if (!out) return PQR_ERR_INVALID_ARG;
   *out = nullptr;
   pqr_ctx* ctx = new pqr_ctx();
@@ -1159,6 +1169,7 @@ pqr_status grouped_impl(int nprob, pqr_ctx* const* ctxs, const double* const* ys
 extern "C" pqr_status pqr_solve(pqr_ctx* ctx, const double* y, double tau, double lambda,
                                 const double* weights, int start, const pqr_result* warm,
                                 pqr_result* out) {
+  Range range_("pqr_solve");
   if (!ctx) return PQR_ERR_INVALID_ARG;
   if (start < PQR_START_ZERO || start > PQR_START_DEVICE) {
     ctx->err = "unknown start mode";
@@ -1173,6 +1184,7 @@ extern "C" pqr_status pqr_solve_grouped(int nprob, pqr_ctx* const* ctxs, const d
                                         const double* taus, const double* lambdas,
                                         const double* const* weights, pqr_result* outs,
                                         pqr_status* statuses) {
+  Range range_("pqr_solve_grouped");
   if (nprob < 1 || !ctxs || !ys || !taus || !lambdas) return PQR_ERR_INVALID_ARG;
   for (int i = 0; i < nprob; ++i)
     if (!ctxs[i]) return PQR_ERR_INVALID_ARG;
@@ -1234,6 +1246,7 @@ pqr_status iterate_impl(pqr_ctx* ctx, const double* y, double tau, double lambda
 extern "C" pqr_status pqr_solve_lla(pqr_ctx* ctx, const double* y, double tau, double lambda,
                                     int penalty, double a, int L, double wfloor,
                                     double* weights_out, int64_t* stage_iters, pqr_result* out) {
+  Range range_("pqr_solve_lla");
   if (!ctx) return PQR_ERR_INVALID_ARG;
   if (penalty != 0 && penalty != 1) {
     ctx->err = "penalty must be 0 (SCAD) or 1 (MCP)";
@@ -1356,6 +1369,7 @@ static pqr_status kkt_impl(pqr_ctx* ctx, const double* y, double tau, double lam
 extern "C" pqr_status pqr_kkt(pqr_ctx* ctx, const double* y, double tau, double lambda,
                               const double* weights, const double* beta_std, const double* theta,
                               double rep[4]) {
+  Range range_("pqr_kkt");
   return kkt_impl(ctx, y, tau, lambda, weights, beta_std, theta, rep, nullptr);
 }
 
@@ -1890,6 +1904,7 @@ extern "C" pqr_status pqr_batch_tiles(pqr_ctx* ctx, int K, int* bgemm_variant, i
 extern "C" pqr_status pqr_solve_batch(pqr_ctx* ctx, const double* y, int K, const double* taus,
                                       const double* lambdas, const double* weights,
                                       pqr_result* outs) {
+  Range range_("pqr_solve_batch");
   if (!ctx) return PQR_ERR_INVALID_ARG;
   return batch_impl(ctx, y, K, taus, lambdas, weights, outs);
 }
@@ -2151,6 +2166,7 @@ extern "C" pqr_status pqr_solve_learned(pqr_ctx* ctx, const double* y, double ta
                                         const double* weights, const float* mlp_params,
                                         double threshold, int max_rounds, pqr_result* out,
                                         pqr_learned_report* rep) {
+  Range range_("pqr_solve_learned");
   if (!ctx) return PQR_ERR_INVALID_ARG;
   const auto t0 = std::chrono::steady_clock::now();
   auto secs = [&]() {
@@ -2215,6 +2231,7 @@ extern "C" pqr_status pqr_solve_screened(pqr_ctx* ctx, const double* y, double t
                                          const double* weights, double lambda_prev,
                                          int64_t budget, int max_rounds, pqr_result* out,
                                          pqr_learned_report* rep) {
+  Range range_("pqr_solve_screened");
   if (!ctx) return PQR_ERR_INVALID_ARG;
   const auto t0 = std::chrono::steady_clock::now();
   TRY(validate_problem(ctx, y, tau, lambda, weights));

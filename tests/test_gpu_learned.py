@@ -105,7 +105,7 @@ def test_learned_warm_start_end_to_end():
     plain = ctx.solve(y, tau, lam)
     thr = learned.prior_threshold(rates)
     assert thr > 0   # inactive rows were subsampled: the raw logits overstate activity
-    lrn = ctx.solve_learned(y, tau, lam, params.data_ptr(), threshold=thr, max_rounds=4)
+    lrn = ctx.solve_learned(y, tau, lam, params.data_ptr(), threshold=thr, max_rounds=8)
     val, _ = lp.highs(X1, y, tau, H.lam_vector(p, lam))
     p_l = pqr.objective(X1, y, lrn["beta_std"], tau, H.lam_vector(p, lam))
     print({k: lrn[k] for k in ("rounds", "fallback", "active_initial", "active_final",
@@ -123,7 +123,7 @@ def test_learned_warm_start_end_to_end():
     # budget (reported: the two are close on these designs), and a useless network
     # (no column proposed: only the 32 forced columns, zero coefficients), which needs
     # more X-passes than the trained one
-    scr = ctx.solve_screened(y, tau, lam, budget=lrn["active_initial"], max_rounds=4)
+    scr = ctx.solve_screened(y, tau, lam, budget=lrn["active_initial"], max_rounds=8)
     passes_screened = scr["reduced_iters"] * scr["active_final"] / p + 2 * scr["rounds"] + 1
     assert scr["rel_gap"] <= tol
     zero = torch.zeros_like(params)
