@@ -207,7 +207,10 @@ pqr_status pqr_iterate(pqr_ctx* ctx, const double* y, double tau, double lambda,
                        double* beta_std, double* z, double* theta);
 
 /* Folded-concave penalties by L-step local linear approximation (Algorithm 2):
- * stage 0 is pqr_solve at unit weights from a zero start; stage l = 1..L solves
+ * stage 0 is pqr_solve at unit weights from `start` (PQR_START_ZERO, or
+ * PQR_START_DEVICE to continue from the state the previous solve on ctx left, e.g.
+ * the last stage at the previous lambda of a path: the warm start of the paper's
+ * path runs; same y and tau); stage l = 1..L solves
  * the weighted problem with lambda_j = lambda w_j, w_j = max(p'_lambda(|b_j|) /
  * lambda, wfloor), b the previous stage's coefficients on the standardized scale
  * and p' the SCAD derivative (eq. scad, penalty 0, a > 2) or the MCP derivative
@@ -223,8 +226,8 @@ pqr_status pqr_iterate(pqr_ctx* ctx, const double* y, double tau, double lambda,
  *               and sweep_launches are summed over all stages
  * Stops at the first stage that does not return PQR_OK and returns its status. */
 pqr_status pqr_solve_lla(pqr_ctx* ctx, const double* y, double tau, double lambda,
-                         int penalty, double a, int L, double wfloor, double* weights_out,
-                         int64_t* stage_iters, pqr_result* out);
+                         int penalty, double a, int L, double wfloor, int start,
+                         double* weights_out, int64_t* stage_iters, pqr_result* out);
 
 /* K problems that share X, y and the weights, with their own (tau_k, lambda_k),
  * solved together (Algorithm 1 for every k, iterated in lockstep).  The back-

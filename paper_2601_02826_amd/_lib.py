@@ -127,7 +127,7 @@ def load():
                                       ctypes.POINTER(_c_dp), ctypes.POINTER(pqr_result),
                                       ctypes.POINTER(ci)]
     lib.pqr_solve_grouped.restype = ci
-    lib.pqr_solve_lla.argtypes = [vp, _c_dp, dbl, dbl, ci, dbl, ci, dbl, _c_dp,
+    lib.pqr_solve_lla.argtypes = [vp, _c_dp, dbl, dbl, ci, dbl, ci, dbl, ci, _c_dp,
                                   ctypes.POINTER(i64), ctypes.POINTER(pqr_result)]
     lib.pqr_solve_lla.restype = ci
     lib.pqr_destroy.argtypes = [vp]
@@ -389,7 +389,7 @@ class Context:
                       reduced_sweep_bytes=rep.reduced_sweep_bytes,
                       reduced_sweep_launches=rep.reduced_sweep_launches)
 
-    def solve_lla(self, y, tau, lam, penalty="scad", a=None, L=1, wfloor=0.0,
+    def solve_lla(self, y, tau, lam, penalty="scad", a=None, L=1, wfloor=0.0, start="zero",
                   allow_not_converged=False):
         """pqr_solve_lla (Algorithm 2).  Returns the last stage's Result with extra keys
         `weights` (p+1) and `stage_iters` (L+1)."""
@@ -404,7 +404,8 @@ class Context:
         its = (ctypes.c_int64 * (L + 1))()
         out = pqr_result(beta=_dptr(beta), beta_std=_dptr(beta_std), z=_dptr(z), theta=_dptr(theta))
         st = self._lib.pqr_solve_lla(self._h, _dptr(_f64(y, self.n)), float(tau), float(lam), kind,
-                                     float(a), int(L), float(wfloor), _dptr(w), its, ctypes.byref(out))
+                                     float(a), int(L), float(wfloor), START[start], _dptr(w), its,
+                                     ctypes.byref(out))
         ok = (PQR_OK, PQR_ERR_NOT_CONVERGED) if allow_not_converged else (PQR_OK,)
         self._check(st, ok)
         return Result(beta=beta, beta_std=beta_std, z=z, theta=theta, iters=out.iters,

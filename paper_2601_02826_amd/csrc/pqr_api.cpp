@@ -1244,7 +1244,7 @@ pqr_status iterate_impl(pqr_ctx* ctx, const double* y, double tau, double lambda
 
 // Algorithm 2: L-step LLA for SCAD / MCP on top of the weighted-l1 solve.
 extern "C" pqr_status pqr_solve_lla(pqr_ctx* ctx, const double* y, double tau, double lambda,
-                                    int penalty, double a, int L, double wfloor,
+                                    int penalty, double a, int L, double wfloor, int start,
                                     double* weights_out, int64_t* stage_iters, pqr_result* out) {
   Range range_("pqr_solve_lla");
   if (!ctx) return PQR_ERR_INVALID_ARG;
@@ -1256,8 +1256,9 @@ extern "C" pqr_status pqr_solve_lla(pqr_ctx* ctx, const double* y, double tau, d
     ctx->err = "SCAD needs a > 2, MCP needs a > 1";
     return PQR_ERR_INVALID_ARG;
   }
-  if (L < 0 || !(wfloor >= 0.0 && wfloor <= 1.0) || !(lambda > 0.0) || !std::isfinite(lambda)) {
-    ctx->err = "pqr_solve_lla needs L >= 0, 0 <= wfloor <= 1 and lambda > 0";
+  if (L < 0 || !(wfloor >= 0.0 && wfloor <= 1.0) || !(lambda > 0.0) || !std::isfinite(lambda) ||
+      (start != PQR_START_ZERO && start != PQR_START_DEVICE)) {
+    ctx->err = "pqr_solve_lla needs L >= 0, 0 <= wfloor <= 1, lambda > 0 and a zero or device start";
     return PQR_ERR_INVALID_ARG;
   }
   const Geom& g = ctx->g;
@@ -1265,8 +1266,8 @@ extern "C" pqr_status pqr_solve_lla(pqr_ctx* ctx, const double* y, double tau, d
   w[0] = 0.0;
   pqr_result tmp{};
   pqr_result* res = out ? out : &tmp;
-  // stage 0: the weighted-l1 solve at unit weights from a zero start
-  pqr_status st = pqr_solve(ctx, y, tau, lambda, nullptr, PQR_START_ZERO, nullptr, res);
+  // stage 0: the weighted-l1 solve at unit weights, from a zero start or the device state
+  pqr_status st = pqr_solve(ctx, y, tau, lambda, nullptr, start, nullptr, res);
   if (stage_iters) stage_iters[0] = res->iters;
   double sweep_ms = res->sweep_ms;
   int64_t sweeps = res->sweep_launches;

@@ -48,12 +48,33 @@ def test_lla_stages(penalty, a, L):
     ctx.close()
 
 
+def test_lla_path_with_device_warm_start():
+    """Along a lambda path, stage 0 of the next lambda may continue from the device state
+    the previous lambda's last stage left (the paper's warm-started paths): the result
+    is certified and its weighted objective equals the zero-start solve's within tol."""
+    import paper_2601_02826_amd as pq
+    n, p, tau, tol = 400, 150, 0.5, 1e-6
+    X, y = H.genotype_problem(n, p, seed=73, n_causal=6)
+    ctx = pq.Context.from_tensor(H.to_device_cols(X.astype(np.uint8), np.uint8), store_fmt="i8",
+                                 G=3, tol_gap=tol, cert_every=100, max_iter=2_000_000,
+                                 iter_prec="f64")
+    lmax = ctx.lambda_max(y, tau)
+    ctx.solve_lla(y, tau, 0.35 * lmax, penalty="mcp", L=1)
+    warm = ctx.solve_lla(y, tau, 0.25 * lmax, penalty="mcp", L=1, start="device")
+    cold = ctx.solve_lla(y, tau, 0.25 * lmax, penalty="mcp", L=1)
+    print(f"stage iterations: warm {warm['stage_iters']}, cold {cold['stage_iters']}")
+    assert warm["rel_gap"] <= tol and cold["rel_gap"] <= tol
+    assert warm["primal"] == pytest.approx(cold["primal"], rel=3 * tol)
+    assert warm["stage_iters"][0] < cold["stage_iters"][0]
+    ctx.close()
+
+
 def test_lla_error_paths():
     import paper_2601_02826_amd as pq
     X, y = H.genotype_problem(300, 100, seed=72)
     ctx = pq.Context.from_tensor(H.to_device_cols(X.astype(np.uint8), np.uint8), store_fmt="i8", G=2)
     for kw in [dict(penalty="scad", a=2.0), dict(penalty="mcp", a=1.0), dict(L=-1),
-               dict(wfloor=-0.1)]:
+               dict(wfloor=-0.1), dict(start="host")]:
         with pytest.raises(pq.PQRError) as e:
             ctx.solve_lla(y, 0.5, 0.05, **kw)
         assert e.value.status == pq.PQR_ERR_INVALID_ARG
