@@ -416,7 +416,7 @@ def bench_path_batched(a):
         "sequential_reference": seq,
         "speedup_vs_sequential": (seq["seconds"] / (elapsed / a.steps)) if seq else None,
         "autotuned_tiles": tiles,
-        "union_product": union_product(tiles, n),
+        "union_product": union_product(tiles, n, f"baxpy_i8_{n // 1000}kx{p // 1000}k_kp{Kp}"),
         "roofline": {"bound": "hbm", "achieved": acc["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": acc["achieved"] / HBM_PEAK_GBS,
                      "traffic": traffic_from_profile(f"bgemm_i8_{n // 1000}kx{p // 1000}k_kp{Kp}",
@@ -437,16 +437,25 @@ def bench_path_batched(a):
 MFMA_INT8_PEAK_TOPS = 5000.0
 
 
-def union_product(tiles, n):
+def union_product(tiles, n, profile=None):
     """k_baxpy at the moment the autotuner timed it: X~ B over the union of nonzero
-    columns, algorithmic bytes = n bytes per union column (int8 store)."""
+    columns, algorithmic bytes = n bytes per union column (int8 store).  With
+    `profile`, the counted HBM traffic over algorithmic bytes of the committed
+    rocprofv3 record profiles/<profile>_traffic.json (if taken on the current source)."""
     v, u = tiles["baxpy_variant"], tiles["union_cols"]
     if v < 0 or u <= 0:
         return None
     ms = tiles["baxpy_ms"][v]
     gbs = n * u / (ms * 1e-3) / 1e9
+    ratio = None
+    if profile:
+        path = os.path.join(ROOT, "profiles", f"{profile}_traffic.json")
+        if os.path.exists(path):
+            rec = json.load(open(path))
+            if rec.get("kernel_source_sha") == source_hash(("kern_batch.hip",)):
+                ratio = rec.get("traffic_over_algorithmic")
     return {"kernel": "k_baxpy", "union_columns": u, "avg_ms": ms, "achieved_GBs": gbs,
-            "frac": gbs / HBM_PEAK_GBS}
+            "frac": gbs / HBM_PEAK_GBS, "traffic_over_algorithmic": ratio}
 
 
 def bgemm_accounting(n, p, K, avg_ms):
@@ -547,6 +556,8 @@ def bench_batched(a):
         "plain_converged": f"{plain_conv}/{K}",
         "speedup_vs_plain": plain_s / (elapsed / a.steps) if plain_s else None,
         "setup_s": setup_s,
+        "autotuned_tiles": ctx.batch_tiles(K),
+        "union_product": union_product(ctx.batch_tiles(K), n),
         "roofline": {"bound": "hbm", "achieved": acc["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": acc["achieved"] / HBM_PEAK_GBS,
                      "traffic": traffic_from_profile(f"bgemm_i8_{n // 1000}kx{p // 1000}k_kp{Kp}",
@@ -900,6 +911,7 @@ def bench_sim(a):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 fits = []
+                iters = 0
                 for k, lam in enumerate(lams):
                     if pen == "lasso":
                         r = ctx.solve(y, tau, lam, start="zero" if k == 0 else "device",
@@ -909,6 +921,7 @@ def bench_sim(a):
                                           start="zero" if k == 0 else "device",
                                           allow_not_converged=True)
                     fits.append(r["beta"].copy())
+                    iters += sum(r["stage_iters"]) if "stage_iters" in r else r["iters"]
                 torch.cuda.synchronize()
                 el = time.perf_counter() - t0
                 best = None
@@ -923,10 +936,11 @@ def bench_sim(a):
                 active = set(np.nonzero(b[1:])[0] + 1)
                 truth = set(int(j) for j in d["support"] if j != 1)
                 rec[(pen, tau)].append(dict(ae=float(np.sum(np.abs(b[1:] - bstar[1:]))),
-                                            p1=truth <= active, p2=1 in active, size=size, time=el))
+                                            p1=truth <= active, p2=1 in active, size=size, time=el,
+                                            iters=iters))
             log(f"replicate {rep + 1}/{a.replicates} tau={tau}: " + ", ".join(
                 f"{pen} AE {rec[(pen, tau)][-1]['ae']:.3f} size {rec[(pen, tau)][-1]['size']} "
-                f"{rec[(pen, tau)][-1]['time']:.1f}s" for pen in pens))
+                f"{rec[(pen, tau)][-1]['time']:.1f}s {rec[(pen, tau)][-1]['iters']} it" for pen in pens))
         ctx.close()
         del Xc
     table = []
@@ -940,7 +954,8 @@ def bench_sim(a):
                               P1=float(np.mean([r["p1"] for r in rs])),
                               P2=float(np.mean([r["p2"] for r in rs])),
                               Size=float(sz.mean()), Size_sd=float(sz.std(ddof=1)) if len(rs) > 1 else 0.0,
-                              Time=float(tm.mean()), Time_sd=float(tm.std(ddof=1)) if len(rs) > 1 else 0.0))
+                              Time=float(tm.mean()), Time_sd=float(tm.std(ddof=1)) if len(rs) > 1 else 0.0,
+                              iters_per_path=float(np.mean([r["iters"] for r in rs]))))
     total = time.perf_counter() - t_all
     out = {
         "metric": "Sec. 7.1 sparse simulation: AE / P1 / P2 / Size / path time per (penalty, tau)",

@@ -101,8 +101,9 @@ typedef struct {
                            the host.  Both run the same kernels in the same order.
                            With opt.profile the kernels are always launched directly. */
   int tile_override;    /* 0 (default) = batched solves choose their launch variants by
-                           timing them (pqr_batch_tiles); 1 + 3 b + a forces back-product
-                           variant b and union-product variant a (0..2 each), for tests */
+                           timing them (pqr_batch_tiles); 1 + PQR_TILE_VARIANTS b + a
+                           forces back-product variant b (0..2) and union-product
+                           variant a (0..2), for tests */
 } pqr_options;
 
 typedef struct pqr_ctx pqr_ctx;
@@ -241,8 +242,10 @@ pqr_status pqr_solve_lla(pqr_ctx* ctx, const double* y, double tau, double lambd
  * whose sum cannot be moved inside the box).  Needs an int8 store with codes 0..127,
  * rows_per_lane 16, FP32 iterates, positive weights and, for the integer sums to
  * stay exact in int32 with 32-bit buffer offsets, n_pad * max(max_code, 1) * 65 <
- * 2^31 and 512 n_pad < 2^31, n_pad = n rounded up to a multiple of 1024
- * (PQR_ERR_UNSUPPORTED otherwise); 1 <= K <= 128.
+ * 2^31, 512 n_pad < 2^31 and p_pad <= 16 * 64 * floor((2^31 - 1) / (64 max(max_code,
+ * 1)) / 64) (the union product's 16 splits; about 4.2 million columns at max_code
+ * 127), n_pad = n rounded up to a multiple of 1024 (PQR_ERR_UNSUPPORTED otherwise);
+ * 1 <= K <= 128.
  *  y, weights  as in pqr_solve;  taus, lambdas  host, K doubles each
  *  outs        host array of K pqr_result (output arrays optional, as in pqr_solve);
  *              beta and z are the final iterate (a certified right-hand side stops
@@ -255,14 +258,17 @@ pqr_status pqr_solve_batch(pqr_ctx* ctx, const double* y, int K, const double* t
                            const double* lambdas, const double* weights, pqr_result* outs);
 
 /* The launch variants the autotuner chose for batched solves of width K on this
- * context, and the mean time (ms) it measured for each of the three candidates of
- * the back-product (bgemm_ms, host, 3 doubles; timed on the first batched solve of
- * that width before its iterations) and of the union product (baxpy_ms; timed at the
- * end of the first chunk of cert_every iterations whose union of nonzero columns
- * holds at least 1024 columns, on that live union; baxpy_variant -1 if none has).  Variant 0 of each is the default configuration; every variant
- * computes identical results.  union_cols receives the number of union columns the
- * union product was timed on (0 if it was not).  Any output pointer may be NULL.
- * PQR_ERR_INVALID_ARG if no batched solve of that width has run on ctx. */
+ * context, and the mean time (ms) it measured for each candidate: the three of the
+ * back-product (bgemm_ms, host, PQR_TILE_VARIANTS doubles, unused entries 0; timed on
+ * the first batched solve of that width before its iterations) and the three of the
+ * union product (baxpy_ms, same size; timed at the end of the first chunk of
+ * cert_every iterations whose union of nonzero columns holds at least 1024 columns,
+ * on that live union; baxpy_variant -1 if none has).  Variant 0 of each is the
+ * default configuration; every variant computes identical results.  union_cols
+ * receives the number of union columns the union product was timed on (0 if it was
+ * not).  Any output pointer may be NULL.  PQR_ERR_INVALID_ARG if no batched solve of
+ * that width has run on ctx. */
+#define PQR_TILE_VARIANTS 8
 pqr_status pqr_batch_tiles(pqr_ctx* ctx, int K, int* bgemm_variant, int* baxpy_variant,
                            double* bgemm_ms, double* baxpy_ms, int64_t* union_cols);
 

@@ -17,6 +17,8 @@ PQR_ERR_NOT_CONVERGED, PQR_ERR_DIVERGED, PQR_ERR_UNSUPPORTED = 4, 5, 6
 FMT = {"f64": 0, "f32": 1, "bf16": 2, "fp8": 3, "i8": 4, "2bit": 5}
 ITER = {"f32": 0, "f64": 1}
 START = {"zero": 0, "host": 1, "device": 2}
+TILE_VARIANTS = 8                      # PQR_TILE_VARIANTS: size of the tuner's time arrays
+BGEMM_VARIANTS, BAXPY_VARIANTS = 3, 3  # launch variants of the back- and union products
 
 _c_dp = ctypes.POINTER(ctypes.c_double)
 
@@ -292,11 +294,12 @@ class Context:
     def batch_tiles(self, K):
         """pqr_batch_tiles: the autotuner's choices and candidate times for width K."""
         bv, av, uc = ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
-        bms, ams = np.zeros(3), np.zeros(3)
+        bms, ams = np.zeros(TILE_VARIANTS), np.zeros(TILE_VARIANTS)
         self._check(self._lib.pqr_batch_tiles(self._h, int(K), ctypes.byref(bv), ctypes.byref(av),
                                               _dptr(bms), _dptr(ams), ctypes.byref(uc)))
-        return dict(bgemm_variant=bv.value, baxpy_variant=av.value, bgemm_ms=bms.tolist(),
-                    baxpy_ms=ams.tolist(), union_cols=uc.value)
+        return dict(bgemm_variant=bv.value, baxpy_variant=av.value,
+                    bgemm_ms=bms[:BGEMM_VARIANTS].tolist(), baxpy_ms=ams[:BAXPY_VARIANTS].tolist(),
+                    union_cols=uc.value)
 
     def kkt_columns(self, y, tau, lam, beta_std, theta, weights=None):
         rep = np.zeros(4)

@@ -13,6 +13,7 @@
 // theta to 7S-1 bits below c_k (S = 3: 2^-20 c_k), instead of FP32 accumulation
 // error.  The sparse products X~ B, the prox maps and the dual steps follow the
 // single right-hand-side kernels.
+#include <atomic>
 #include <climits>
 #include <utility>
 
@@ -23,6 +24,7 @@ namespace pqr {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef unsigned v4u __attribute__((ext_vector_type(4)));
+typedef int v2i __attribute__((ext_vector_type(2)));
 
 constexpr int kBS = 3;                  // digit slices of theta
 
@@ -453,9 +455,11 @@ __global__ __launch_bounds__(1024) void k_bscatter(int64_t ngroups, BatchBufs b,
 // column scale, b'_kj = beta_kj / s_j, are written in fixed point as
 // U_kj = round(b'_kj / d_k * 2^27) with d_k a power of two >= max_j |b'_kj|, cut
 // into four balanced base-128 digits (|digit| <= 64); every product and sum of
-// a slice is exact in int32, so S_ik = d_k 2^-27 (sum_j x_ij U_kj - sum_j m_j U_kj)
-// is exactly X~ times the quantised coefficients (2^-28 d_k each), combined in
-// int64 and FP64 per split of the union.
+// a slice is exact in int32 (at most (2^31 - 1) / (64 max_code) columns per split
+// of the union), each split's sum_j x_ij U_kj is combined exactly in int64 and the
+// splits are added in int64, so S_ik = d_k 2^-27 (sum_j x_ij U_kj - sum_j m_j U_kj)
+// is exactly X~ times the quantised coefficients (2^-28 d_k each) up to one final
+// FP64 rounding, whatever the number of splits.
 // ---------------------------------------------------------------------------
 constexpr int kCS = 4;                  // digit slices of the coefficients
 constexpr int kDigitBlocks = 256;       // blocks of the coefficient digit kernels
@@ -555,14 +559,17 @@ __global__ __launch_bounds__(256) void k_bbdigits(Geom g, BatchBufs b, int Kp) {
 // the caches deliver them once per WPB * 16 RT rows instead of once per
 // wavefront.  Splits of the union along grid.y write FP64 partials.
 constexpr int kXStride = 68;   // LDS bytes per staged column (64 rows + 4, bank spread)
-constexpr int kAxPrefetch = 2; // 64-column steps loaded ahead of the union product's MFMAs
+constexpr int kXStrideTr = 72; // the same for 8-byte transposing reads (8-byte aligned)
+constexpr bool kBaxpyTr = true;  // transposing LDS reads (gfx950) for the B operand
+constexpr int kAxSets = 3;     // union product: X loaded this many 64-column steps ahead
 
-template <int RT, int NRT, int WPB>
+template <int RT, int NRT, int WPB, bool TR = kBaxpyTr>
 __global__ __launch_bounds__(64 * WPB) void k_baxpy(Geom g, BatchBufs b, int smax, int min_per) {
+  constexpr int kXS = TR ? kXStrideTr : kXStride;
   constexpr int Kp = NRT * 16;
   constexpr int kDig = NRT * kCS * 64;                  // uint4 digit fragments per step
   constexpr int kDigPer = (kDig + 64 * WPB - 1) / (64 * WPB);
-  __shared__ uint32_t xs[WPB][64 * kXStride / 4];
+  __shared__ __attribute__((aligned(16))) uint32_t xs[WPB][64 * kXS / 4];
   __shared__ uint4 dg[2][kDig];                         // [buffer][(r * kCS + sl) * 64 + lane]
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -587,18 +594,24 @@ __global__ __launch_bounds__(64 * WPB) void k_baxpy(Geom g, BatchBufs b, int sma
   uint32_t* xw = xs[wv];
   const int kb = lane >> 4, m = lane & 15;
   const int nvg = (count + 15) / 16;                    // virtual groups with digits
-  // This thread's rows of union entry 64 qd + lane (past the count it re-reads the
-  // last entry; its digits are zero).
-  auto fetch_x = [&](int qd, uint4 (&xv)[RT]) {
+  // The column of union entry 64 qd + lane (past the count it re-reads the last
+  // entry; its digits are zero), and this thread's rows of a column.  Entries are
+  // loaded two steps before the rows they address: the wait for an entry then
+  // covers only loads issued before it, never the X loads still in flight.
+  auto fetch_j = [&](int qd) -> int {
     const int il = 64 * qd + lane < count ? 64 * qd + lane : count - 1;
-    const int64_t jl = b.list[il];
+    return b.list[il];
+  };
+  auto fetch_x = [&](int64_t jl, uint4 (&xv)[RT]) {
     const uint8_t* src = g.seg(jl, ch) + roff;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) xv[rt] = *reinterpret_cast<const uint4*>(src + 16 * rt);
   };
   // This thread's share of the step's digits: fragment f = (r * kCS + sl) * 64 + l
   // holds the A operand of MFMA lane l: digits of (rhs r*16 + l % 16, virtual group
-  // 4 qd + l / 16), zero past the last virtual group.
+  // 4 qd + l / 16), zero past the last virtual group and for steps past this split
+  // (applied when stored, so that no instruction waits for a digit load before the
+  // step that stores it).
   auto fetch_d = [&](int qd, uint4 (&dv)[kDigPer]) {
 #pragma unroll
     for (int u = 0; u < kDigPer; ++u) {
@@ -607,88 +620,109 @@ __global__ __launch_bounds__(64 * WPB) void k_baxpy(Geom g, BatchBufs b, int sma
       const int l = fl & 63, sl = (fl >> 6) % kCS, r = (fl >> 6) / kCS;
       const int el = 4 * qd + (l >> 4);
       const int64_t ec = el < nvg ? el : nvg - 1;
-      const uint4 v = *reinterpret_cast<const uint4*>(
+      dv[u] = *reinterpret_cast<const uint4*>(
           b.bd + (((int64_t)ec * Kp + r * 16 + (l & 15)) * kCS + sl) * kGroup);
-      dv[u] = el < nvg ? v : uint4{0, 0, 0, 0};
     }
   };
-  auto store_d = [&](int buf, const uint4 (&dv)[kDigPer]) {
+  auto store_d = [&](int buf, const uint4 (&dv)[kDigPer], int qd) {
 #pragma unroll
     for (int u = 0; u < kDigPer; ++u) {
       const int f = tid + u * 64 * WPB;
-      if (f < kDig) dg[buf][f] = dv[u];
+      if (f < kDig)
+        dg[buf][f] = qd < q1 && 4 * qd + ((f & 63) >> 4) < nvg ? dv[u] : uint4{0, 0, 0, 0};
     }
   };
-  // Loads run NPF steps ahead of the MFMAs (xq[i], dq[i]: step qd + 1 + i), so that
-  // NPF + 1 steps of X are in flight per wavefront across the block's barriers.
-  uint4 xv[RT];
-  uint4 xq[kAxPrefetch][RT];
-  uint4 dq[kAxPrefetch][kDigPer];
+  // NS register sets in rotation, the step's set a compile-time index (the loop body
+  // is NS steps): at step qd set c = (qd - q0) % NS holds X of step qd, which is
+  // staged, and is then refilled with X and digits of step qd + NS, so that X loads
+  // run NS steps ahead of their MFMAs with no register moves (a move would wait for
+  // its load).  The column index of step qd + NS was loaded at step qd - NS.  Per
+  // step the digit loads come first and the index load last, so that the waits
+  // (store of step qd + 1's digits, index of step qd + NS) never cover a later X load.
+  // Every step of the body runs, also past q1 (on the last step's columns with zero
+  // digits): a skipped step would leave the compiler's wait counts at zero.
+  constexpr int NS = kAxSets;
+  uint4 xset[NS][RT];
+  uint4 dset[NS][kDigPer];
+  int jset[NS];
+  auto clampq = [&](int q) { return q < q1 ? q : q1 - 1; };
   if (q0 < q1) {
-    uint4 d0[kDigPer];
-    fetch_x(q0, xv);
-    fetch_d(q0, d0);
-    store_d(q0 & 1, d0);
-#pragma unroll
-    for (int i = 0; i < kAxPrefetch; ++i) {
-      const int qi = q0 + 1 + i < q1 ? q0 + 1 + i : q1 - 1;
-      fetch_x(qi, xq[i]);
-      fetch_d(qi, dq[i]);
-    }
+    // (the index loads first: the loop's wait counts hold from its first step on)
+    static_for<NS>([&](auto I) { jset[I.value] = fetch_j(clampq(q0 + NS + I.value)); });
+    static_for<NS>([&](auto I) {
+      const int q = clampq(q0 + I.value);
+      fetch_d(q, dset[I.value]);
+      fetch_x(fetch_j(q), xset[I.value]);
+    });
+    store_d(q0 & 1, dset[0], q0);
   }
   __syncthreads();
-  for (int qd = q0; qd < q1; ++qd) {
-    // stage: column `lane` at xw[lane * kXStride / 4 ...], rows 0 .. 16 RT - 1
+  for (int qb = q0; qb < q1; qb += NS) {
+    static_for<NS>([&](auto I) {
+      constexpr int c = I.value;
+      const int qd = qb + c;
+      {
+        // stage: column `lane` at xw[lane * kXS / 4 ...], rows 0 .. 16 RT - 1
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-      uint32_t* d = xw + lane * (kXStride / 4) + 4 * rt;
-      d[0] = xv[rt].x; d[1] = xv[rt].y; d[2] = xv[rt].z; d[3] = xv[rt].w;
-    }
-    __builtin_amdgcn_wave_barrier();
-    const uint8_t* xb = reinterpret_cast<const uint8_t*>(xw);
-    const uint4* dgb = dg[qd & 1];
-    v4i bf[RT];
+        for (int rt = 0; rt < RT; ++rt) {
+          uint32_t* d = xw + lane * (kXS / 4) + 4 * rt;
+          d[0] = xset[c][rt].x; d[1] = xset[c][rt].y; d[2] = xset[c][rt].z; d[3] = xset[c][rt].w;
+        }
+        __builtin_amdgcn_wave_barrier();
+        const uint8_t* xb = reinterpret_cast<const uint8_t*>(xw);
+        const uint4* dgb = dg[qd & 1];
+        v4i bf[RT];
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-      // B operand: row 16 rt + m, columns 16 kb + 0..15
-      uint32_t w[4];
+        for (int rt = 0; rt < RT; ++rt) {
+          // B operand: row 16 rt + m, columns 16 kb + 0..15
+          if constexpr (TR) {
+            // transposing 8-byte reads (ds_read_b64_tr_b8): in each group of 16
+            // lanes, byte b of the result of lane 16 g + 8 e + j is byte j of what
+            // lane 16 g + 2 b + e read.  Lane L reads rows 8 (L & 1) .. +7 of column
+            // 16 (L >> 4) + 8 h + ((L >> 1) & 7), so lane (m, kb) receives row m of
+            // columns 16 kb + 8 h .. +7 in order.
+            v2i r[2];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint8_t* p = xb + (16 * kb + 4 * q) * kXStride + 16 * rt + m;
-        w[q] = (uint32_t)p[0] | ((uint32_t)p[kXStride] << 8) | ((uint32_t)p[2 * kXStride] << 16) |
-               ((uint32_t)p[3 * kXStride] << 24);
+            for (int h = 0; h < 2; ++h)
+              r[h] = __builtin_amdgcn_ds_read_tr8_b64_v2i32(
+                  (__attribute__((address_space(3))) v2i*)(xb +
+                      (16 * kb + 8 * h + ((lane >> 1) & 7)) * kXS + 8 * (lane & 1) + 16 * rt));
+            bf[rt] = v4i{r[0].x, r[0].y, r[1].x, r[1].y};
+          } else {
+            uint32_t w[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const uint8_t* p = xb + (16 * kb + 4 * q) * kXS + 16 * rt + m;
+              w[q] = (uint32_t)p[0] | ((uint32_t)p[kXS] << 8) | ((uint32_t)p[2 * kXS] << 16) |
+                     ((uint32_t)p[3 * kXS] << 24);
+            }
+            bf[rt] = v4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < NRT; ++r)
+#pragma unroll
+          for (int sl = 0; sl < kCS; ++sl) {
+            const uint4 a4 = dgb[(r * kCS + sl) * 64 + lane];
+            const v4i af = v4i{(int)a4.x, (int)a4.y, (int)a4.z, (int)a4.w};
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+              acc[rt][r][sl] =
+                  __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf[rt], acc[rt][r][sl], 0, 0, 0);
+          }
+        __builtin_amdgcn_wave_barrier();
+        // every wavefront has finished reading buffer (qd + 1) & 1 (step qd - 1)
+        // before the barrier that ended that step, so it can be refilled now
+        store_d((qd + 1) & 1, dset[(c + 1) % NS], qd + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        const int jx = jset[c];
+        fetch_d(clampq(qd + NS), dset[c]);
+        fetch_x(jx, xset[c]);
+        jset[c] = fetch_j(clampq(qd + 2 * NS));
+        __builtin_amdgcn_sched_barrier(0);
+        __syncthreads();
       }
-      bf[rt] = v4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
-    }
-#pragma unroll
-    for (int r = 0; r < NRT; ++r)
-#pragma unroll
-      for (int sl = 0; sl < kCS; ++sl) {
-        const uint4 a4 = dgb[(r * kCS + sl) * 64 + lane];
-        const v4i af = v4i{(int)a4.x, (int)a4.y, (int)a4.z, (int)a4.w};
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-          acc[rt][r][sl] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf[rt], acc[rt][r][sl], 0, 0, 0);
-      }
-    __builtin_amdgcn_wave_barrier();
-    // every wavefront has finished reading buffer (qd + 1) & 1 (step qd - 1) before
-    // the barrier that ended that step, so it can be refilled now
-    store_d((qd + 1) & 1, dq[0]);
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt) xv[rt] = xq[0][rt];
-#pragma unroll
-    for (int i = 0; i + 1 < kAxPrefetch; ++i) {
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt) xq[i][rt] = xq[i + 1][rt];
-#pragma unroll
-      for (int u = 0; u < kDigPer; ++u) dq[i][u] = dq[i + 1][u];
-    }
-    {
-      const int qf = qd + 1 + kAxPrefetch < q1 ? qd + 1 + kAxPrefetch : q1 - 1;
-      fetch_x(qf, xq[kAxPrefetch - 1]);
-      fetch_d(qf, dq[kAxPrefetch - 1]);
-    }
-    __syncthreads();
+    });
   }
   // lane holds C[rhs = r*16 + 4 kb + i][row = rw + 16 rt + m]
 #pragma unroll
@@ -696,13 +730,12 @@ __global__ __launch_bounds__(64 * WPB) void k_baxpy(Geom g, BatchBufs b, int sma
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int k = r * 16 + 4 * kb + i;
-      const double unit = b.bscale[k] / (double)(1ll << kCBits);
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
         long long P = 0;
 #pragma unroll
         for (int sl = 0; sl < kCS; ++sl) P = P * 128 + (long long)acc[rt][r][sl][i];
-        b.partial[((int64_t)split * Kp + k) * g.n_pad + rw + 16 * rt + m] = (double)P * unit;
+        b.partial[((int64_t)split * Kp + k) * g.n_pad + rw + 16 * rt + m] = P;
       }
     }
 }
@@ -726,8 +759,10 @@ __global__ __launch_bounds__(256) void k_bupdate(BatchBufs b, int64_t n, int64_t
   }
   __syncthreads();
   if (i < n && k < b.K && b.kact[k]) {
-    double s = b.beta0[k] - (*b.count > 0 ? offk : 0.0);
-    for (int sp = 0; sp < seff; ++sp) s += b.partial[((int64_t)sp * Kp + k) * n_pad + i];
+    long long P = 0;   // exact: the splits' integer sums
+    for (int sp = 0; sp < seff; ++sp) P += b.partial[((int64_t)sp * Kp + k) * n_pad + i];
+    const double s = b.beta0[k] - (*b.count > 0 ? offk : 0.0) +
+                     (double)P * (b.bscale[k] / (double)(1ll << kCBits));
     const int64_t o = (int64_t)k * n_pad + i;
     const float tau = b.tau[k];
     const float muf = (float)mu;
@@ -924,13 +959,12 @@ hipError_t launch_cert_pass(const Geom& g, const CertArgs& c, int Kc, hipStream_
 // GW = 2 (half the accumulators, twice the blocks), variant 2 for 1 or 2 tiles a
 // longer digit tile (SPT 4, one barrier per 256 rows) or the shared-A form.
 // DL = ceil(12 SPT Kp / (64 WPB)) digit loads per thread and tile.
-int bgemm_variants() { return 3; }
 
 hipError_t launch_bgemm_variant(const Geom& g, const BatchBufs& b, int Kp, int v, hipStream_t s,
                                 hipEvent_t ev0, hipEvent_t ev1) {
   const CertArgs c{};
   const int nrt = Kp / 16;
-  if (v < 0 || v > 2) return hipErrorInvalidValue;
+  if (v < 0 || v >= bgemm_variants()) return hipErrorInvalidValue;
   switch (nrt) {
     case 1:
       if (v == 0) return launch_bgemm<1, 4, 1, 2, 8, 2, kBS, false>(g, b, c, Kp, 1, s, ev0, ev1);
@@ -959,57 +993,90 @@ hipError_t launch_bgemm_variant(const Geom& g, const BatchBufs& b, int Kp, int v
 // Union product: rows per wavefront 16 RT with RT * NRT * 16 <= 128 accumulator
 // registers; variants 0, 1, 2 = blocks of 8, 4 and 16 wavefronts sharing the staged
 // digits (n_pad is a multiple of 1024 >= 16 W RT rows); splits of the union along y.
-int baxpy_variants() { return 3; }
+// The split count (the results do not depend on it: exact integer split sums) is
+// the largest that lets every block of the grid be resident at once, so that a
+// large union runs as one round of blocks instead of ending in a partly empty
+// round; never fewer than smin (the int32 limit on columns per split), never more
+// than kBaxpySplits (the partial buffer).
+static int device_cus() {
+  static std::atomic<int> cus[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  int c = cus[dev].load(std::memory_order_relaxed);
+  if (c <= 0) {
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1)
+      c = 256;
+    cus[dev].store(c, std::memory_order_relaxed);
+  }
+  return c;
+}
+
+template <int RT, int NRT, int W>
+static hipError_t launch_baxpy_k(const Geom& g, const BatchBufs& b, int smin, int min_per,
+                                 hipStream_t s, int* splits) {
+  if (smin > kBaxpySplits) return hipErrorInvalidValue;
+  auto kern = k_baxpy<RT, NRT, W>;
+  static std::atomic<int> per_cu{0};   // resident blocks per CU (one code object: gfx950)
+  int bpc = per_cu.load(std::memory_order_relaxed);
+  if (bpc <= 0) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, reinterpret_cast<const void*>(kern),
+                                                     64 * W, 0) != hipSuccess || bpc < 1)
+      bpc = 1;
+    per_cu.store(bpc, std::memory_order_relaxed);
+  }
+  const int64_t rowblocks = g.n_pad / (16 * W * RT);
+  int64_t sp = (int64_t)device_cus() * bpc / (rowblocks > 0 ? rowblocks : 1);
+  sp = sp < smin ? smin : sp;
+  sp = sp < 1 ? 1 : (sp > kBaxpySplits ? kBaxpySplits : sp);
+  hipLaunchKernelGGL(kern, dim3((unsigned)rowblocks, (unsigned)sp), dim3(64 * W), 0, s, g, b,
+                     (int)sp, min_per);
+  if (splits) *splits = (int)sp;
+  return hipGetLastError();
+}
 
 template <int W>
-static hipError_t launch_baxpy_w(const Geom& g, const BatchBufs& b, int nrt, int smax, int min_per,
-                                 hipStream_t s) {
-  const unsigned smx = (unsigned)smax;
-  auto rows = [&](int rt) { return dim3((unsigned)(g.n_pad / (16 * W * rt)), smx); };
-  const dim3 blk(64 * W);
+static hipError_t launch_baxpy_w(const Geom& g, const BatchBufs& b, int nrt, int smin, int min_per,
+                                 hipStream_t s, int* splits) {
   switch (nrt) {
-    case 1: hipLaunchKernelGGL((k_baxpy<4, 1, W>), rows(4), blk, 0, s, g, b, smax, min_per); break;
-    case 2: hipLaunchKernelGGL((k_baxpy<2, 2, W>), rows(2), blk, 0, s, g, b, smax, min_per); break;
-    case 3: hipLaunchKernelGGL((k_baxpy<1, 3, W>), rows(1), blk, 0, s, g, b, smax, min_per); break;
-    case 4: hipLaunchKernelGGL((k_baxpy<1, 4, W>), rows(1), blk, 0, s, g, b, smax, min_per); break;
-    case 5: hipLaunchKernelGGL((k_baxpy<1, 5, W>), rows(1), blk, 0, s, g, b, smax, min_per); break;
-    case 6: hipLaunchKernelGGL((k_baxpy<1, 6, W>), rows(1), blk, 0, s, g, b, smax, min_per); break;
-    case 7: hipLaunchKernelGGL((k_baxpy<1, 7, W>), rows(1), blk, 0, s, g, b, smax, min_per); break;
-    case 8: hipLaunchKernelGGL((k_baxpy<1, 8, W>), rows(1), blk, 0, s, g, b, smax, min_per); break;
-    default: return hipErrorInvalidValue;
+    case 1: return launch_baxpy_k<4, 1, W>(g, b, smin, min_per, s, splits);
+    case 2: return launch_baxpy_k<2, 2, W>(g, b, smin, min_per, s, splits);
+    case 3: return launch_baxpy_k<1, 3, W>(g, b, smin, min_per, s, splits);
+    case 4: return launch_baxpy_k<1, 4, W>(g, b, smin, min_per, s, splits);
+    case 5: return launch_baxpy_k<1, 5, W>(g, b, smin, min_per, s, splits);
+    case 6: return launch_baxpy_k<1, 6, W>(g, b, smin, min_per, s, splits);
+    case 7: return launch_baxpy_k<1, 7, W>(g, b, smin, min_per, s, splits);
+    case 8: return launch_baxpy_k<1, 8, W>(g, b, smin, min_per, s, splits);
   }
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 // 16-wavefront blocks cap a wavefront at 128 VGPRs, which from 5 tiles on would spill
-// the accumulators: there variant 2 is the 8-wavefront block.
+// the accumulators (there variant 2 is the 8-wavefront block) and at one tile the
+// three X register sets of 64 rows (so one tile takes 32 rows per wavefront).
 template <>
-hipError_t launch_baxpy_w<16>(const Geom& g, const BatchBufs& b, int nrt, int smax, int min_per,
-                              hipStream_t s) {
-  const dim3 blk(64 * 16);
-  auto rows = [&](int rt) { return dim3((unsigned)(g.n_pad / (16 * 16 * rt)), (unsigned)smax); };
+hipError_t launch_baxpy_w<16>(const Geom& g, const BatchBufs& b, int nrt, int smin, int min_per,
+                              hipStream_t s, int* splits) {
   switch (nrt) {
-    case 1: hipLaunchKernelGGL((k_baxpy<4, 1, 16>), rows(4), blk, 0, s, g, b, smax, min_per); break;
-    case 2: hipLaunchKernelGGL((k_baxpy<2, 2, 16>), rows(2), blk, 0, s, g, b, smax, min_per); break;
-    case 3: hipLaunchKernelGGL((k_baxpy<1, 3, 16>), rows(1), blk, 0, s, g, b, smax, min_per); break;
-    case 4: hipLaunchKernelGGL((k_baxpy<1, 4, 16>), rows(1), blk, 0, s, g, b, smax, min_per); break;
-    default: return launch_baxpy_w<8>(g, b, nrt, smax, min_per, s);
+    case 1: return launch_baxpy_k<2, 1, 16>(g, b, smin, min_per, s, splits);
+    case 2: return launch_baxpy_k<2, 2, 16>(g, b, smin, min_per, s, splits);
+    case 3: return launch_baxpy_k<1, 3, 16>(g, b, smin, min_per, s, splits);
+    case 4: return launch_baxpy_k<1, 4, 16>(g, b, smin, min_per, s, splits);
   }
-  return hipGetLastError();
+  return launch_baxpy_w<8>(g, b, nrt, smin, min_per, s, splits);
 }
 
-hipError_t launch_baxpy_variant(const Geom& g, const BatchBufs& b, int Kp, int smax, int min_per,
-                                int v, hipStream_t s) {
+hipError_t launch_baxpy_variant(const Geom& g, const BatchBufs& b, int Kp, int smin, int min_per,
+                                int v, hipStream_t s, int* splits) {
   if (g.n_pad % 1024) return hipErrorInvalidValue;
   const int nrt = Kp / 16;
-  if (v == 0) return launch_baxpy_w<8>(g, b, nrt, smax, min_per, s);
-  if (v == 1) return launch_baxpy_w<4>(g, b, nrt, smax, min_per, s);
-  if (v == 2) return launch_baxpy_w<16>(g, b, nrt, smax, min_per, s);
+  if (v == 0) return launch_baxpy_w<8>(g, b, nrt, smin, min_per, s, splits);
+  if (v == 1) return launch_baxpy_w<4>(g, b, nrt, smin, min_per, s, splits);
+  if (v == 2) return launch_baxpy_w<16>(g, b, nrt, smin, min_per, s, splits);
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_batch_iteration(const Geom& g, const BatchBufs& b, int Kp, double mu,
-                                  double sigma, double eta0, int smax, int min_per,
+                                  double sigma, double eta0, int smin, int min_per,
                                   const BatchTiles& tiles, hipStream_t s, hipEvent_t ev0,
                                   hipEvent_t ev1) {
   if (g.fmt != I8 || g.rpl != 16 || Kp % 16 || Kp > 128) return hipErrorInvalidValue;
@@ -1024,7 +1091,8 @@ hipError_t launch_batch_iteration(const Geom& g, const BatchBufs& b, int Kp, dou
                      eta0, Kp);
   hipLaunchKernelGGL(k_bbmax, dim3(kDigitBlocks), dim3(256), 0, s, g, b, Kp);
   hipLaunchKernelGGL(k_bbdigits, dim3(kDigitBlocks), dim3(256), 0, s, g, b, Kp);
-  e = launch_baxpy_variant(g, b, Kp, smax, min_per, tiles.baxpy, s);
+  int smax = 0;
+  e = launch_baxpy_variant(g, b, Kp, smin, min_per, tiles.baxpy, s, &smax);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_bupdate, dim3(nb, Kp), dim3(256), 0, s, b, g.n, g.n_pad, Kp, mu, sigma,
                      smax, min_per);

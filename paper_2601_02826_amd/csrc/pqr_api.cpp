@@ -1411,7 +1411,6 @@ pqr_status batch_alloc(pqr_ctx* ctx, int Kp) {
   const Geom& g = ctx->g;
   BatchBufs& b = ctx->bb;
   const int64_t nblk = g.n_pad / 256, ng = g.ngroups();
-  const int smax = 16;
   TRY(dalloc(ctx, &b.beta, (size_t)Kp * g.p_pad * 4));
   float* w;
   TRY(dalloc(ctx, &w, g.p_pad * 4));
@@ -1439,7 +1438,7 @@ pqr_status batch_alloc(pqr_ctx* ctx, int Kp) {
   TRY(dalloc(ctx, &b.list, (size_t)g.p_pad * 4));
   TRY(dalloc(ctx, &b.bcnt, kCompactBlocks * 4));
   TRY(dalloc(ctx, &b.count, 64));
-  TRY(dalloc(ctx, &b.partial, (size_t)smax * Kp * g.n_pad * 8));
+  TRY(dalloc(ctx, &b.partial, (size_t)kBaxpySplits * Kp * g.n_pad * 8));
   TRY(dalloc(ctx, &b.bpart, (size_t)nblk * Kp * 8 * 8));
   TRY(dalloc(ctx, &b.bd, (size_t)ng * Kp * 64));
   TRY(dalloc(ctx, &b.pmax, (size_t)256 * Kp * 8));
@@ -1507,6 +1506,18 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
                std::to_string(ctx->max_code) + ")";
     return PQR_ERR_UNSUPPORTED;
   }
+  // fewest splits of the union product that keep its int32 slice sums exact: a
+  // split of the (at most p_pad) union columns holds at most lim_steps 64-column steps
+  const int min_per = 4;
+  const int64_t lim_steps = (((int64_t)1 << 31) - 1) / (64 * std::max(ctx->max_code, 1)) / 64;
+  const int smin = (int)(((g.p_pad + 63) / 64 + lim_steps - 1) / lim_steps);
+  if (smin > kBaxpySplits) {
+    ctx->err = "batched solves: the union product needs " + std::to_string(smin) +
+               " splits of at most (2^31 - 1) / (64 max_code) columns, more than " +
+               std::to_string(kBaxpySplits) + " (p_pad " + std::to_string(g.p_pad) +
+               ", max code " + std::to_string(ctx->max_code) + ")";
+    return PQR_ERR_UNSUPPORTED;
+  }
   const int Kp = (K + 15) / 16 * 16;
   TRY(batch_alloc(ctx, Kp));
   BatchBufs b = ctx->bb;
@@ -1538,12 +1549,12 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
   pqr_ctx::TileChoice& tc = ctx->tiles[Kp];
   if (ctx->opt.tile_override > 0) {
     const int o = ctx->opt.tile_override - 1;
-    if (o / 3 >= bgemm_variants() || o % 3 >= baxpy_variants()) {
+    if (o / PQR_TILE_VARIANTS >= bgemm_variants() || o % PQR_TILE_VARIANTS >= baxpy_variants()) {
       ctx->err = "tile_override out of range";
       return PQR_ERR_INVALID_ARG;
     }
-    tc.tiles.bgemm = o / 3;
-    tc.tiles.baxpy = o % 3;
+    tc.tiles.bgemm = o / PQR_TILE_VARIANTS;
+    tc.tiles.baxpy = o % PQR_TILE_VARIANTS;
     tc.bgemm_done = tc.baxpy_done = true;
   }
   auto time_launches = [&](auto&& launch, double* ms) -> pqr_status {
@@ -1583,7 +1594,6 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
   ctx->have_state = false;   // the single right-hand-side state is not the batch's
 
   const double sigma = mu / (ctx->G + 1.0);
-  const int smax = 16, min_per = 4;
   std::vector<double> best_dual(K, -INFINITY), primal(K, INFINITY), rel(K, INFINITY);
   std::vector<char> done(K, 0);
   std::vector<int64_t> done_it(K, 0);   // iteration at which right-hand side k was certified
@@ -1775,7 +1785,7 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
     TRY(push_masks());
     const int64_t chunk = std::min<int64_t>(ctx->opt.cert_every, ctx->opt.max_iter - it);
     for (int64_t q = 0; q < chunk; ++q)
-      HIPCHK(launch_batch_iteration(g, b, Kp, mu, sigma, eta[0], smax, min_per, tc.tiles, s,
+      HIPCHK(launch_batch_iteration(g, b, Kp, mu, sigma, eta[0], smin, min_per, tc.tiles, s,
                                     prof ? ctx->events[2 * q] : nullptr,
                                     prof ? ctx->events[2 * q + 1] : nullptr));
     it += chunk;
@@ -1792,7 +1802,7 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
       tc.baxpy_ms.assign(baxpy_variants(), 0.0);
       int best = 0;
       for (int v = 0; v < baxpy_variants(); ++v) {
-        TRY(time_launches([&]() { return launch_baxpy_variant(g, b, Kp, smax, min_per, v, s); },
+        TRY(time_launches([&]() { return launch_baxpy_variant(g, b, Kp, smin, min_per, v, s); },
                           &tc.baxpy_ms[v]));
         if (tc.baxpy_ms[v] < tc.baxpy_ms[best]) best = v;
       }
@@ -1882,6 +1892,9 @@ pqr_status batch_impl(pqr_ctx* ctx, const double* y, int K, const double* taus,
 
 }  // namespace
 
+static_assert(kBgemmVariants <= PQR_TILE_VARIANTS && kBaxpyVariants <= PQR_TILE_VARIANTS,
+              "more launch variants than pqr_batch_tiles reports");
+
 extern "C" pqr_status pqr_batch_tiles(pqr_ctx* ctx, int K, int* bgemm_variant, int* baxpy_variant,
                                       double* bgemm_ms, double* baxpy_ms, int64_t* union_cols) {
   if (!ctx || K < 1 || K > 128) return PQR_ERR_INVALID_ARG;
@@ -1895,7 +1908,7 @@ extern "C" pqr_status pqr_batch_tiles(pqr_ctx* ctx, int K, int* bgemm_variant, i
   if (bgemm_variant) *bgemm_variant = tc.tiles.bgemm;
   if (baxpy_variant) *baxpy_variant = tc.baxpy_done ? tc.tiles.baxpy : -1;
   if (union_cols) *union_cols = tc.union_cols;
-  for (int v = 0; v < 3; ++v) {
+  for (int v = 0; v < PQR_TILE_VARIANTS; ++v) {
     if (bgemm_ms) bgemm_ms[v] = v < (int)tc.bgemm_ms.size() ? tc.bgemm_ms[v] : 0.0;
     if (baxpy_ms) baxpy_ms[v] = v < (int)tc.baxpy_ms.size() ? tc.baxpy_ms[v] : 0.0;
   }

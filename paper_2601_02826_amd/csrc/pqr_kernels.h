@@ -207,7 +207,7 @@ struct BatchBufs {
   int* list;            // p_pad: union of the nonzero columns, increasing
   int* bcnt;            // kCompactBlocks
   int* count;           // 1
-  double* partial;      // smax x Kp x n_pad
+  long long* partial;   // kBaxpySplits x Kp x n_pad exact integer split sums of X B
   double* bpart;        // (n_pad/256) x Kp x 8
   int8_t* bd;           // ngroups x Kp x 4 x 16: digit slices of the coefficients of
                         // the union columns (list order), for X~ B on the matrix cores
@@ -222,16 +222,20 @@ struct BatchBufs {
 struct BatchTiles {
   int bgemm = 0, baxpy = 0;
 };
-int bgemm_variants();
-int baxpy_variants();
+constexpr int kBgemmVariants = 3, kBaxpyVariants = 3;
+constexpr int kBaxpySplits = 16;   // most splits of the union product (partial buffer)
+inline int bgemm_variants() { return kBgemmVariants; }
+inline int baxpy_variants() { return kBaxpyVariants; }
 hipError_t launch_bgemm_variant(const Geom& g, const BatchBufs& b, int Kp, int v, hipStream_t s,
                                 hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
-hipError_t launch_baxpy_variant(const Geom& g, const BatchBufs& b, int Kp, int smax, int min_per,
-                                int v, hipStream_t s);
+// smin: fewest splits of the union (int32 exactness); the split count used (also
+// needed by the update kernel) is returned in *splits
+hipError_t launch_baxpy_variant(const Geom& g, const BatchBufs& b, int Kp, int smin, int min_per,
+                                int v, hipStream_t s, int* splits = nullptr);
 // One batched iteration; with non-null events, ev0/ev1 are recorded around the
 // back-product kernel (k_bgemm).
 hipError_t launch_batch_iteration(const Geom& g, const BatchBufs& b, int Kp, double mu,
-                                  double sigma, double eta0, int smax, int min_per,
+                                  double sigma, double eta0, int smin, int min_per,
                                   const BatchTiles& tiles, hipStream_t s, hipEvent_t ev0 = nullptr,
                                   hipEvent_t ev1 = nullptr);
 hipError_t launch_batch_zero(const Geom& g, const BatchBufs& b, int Kp, hipStream_t s);

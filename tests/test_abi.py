@@ -38,3 +38,17 @@ def test_binding_has_no_cpu_path():
             L.load()
     finally:
         L.LIB_PATH, L._lib = saved
+
+
+def test_binding_constants_match_the_header():
+    """Sizes the binding hard-codes are the header's (and the kernels' launch variant
+    counts fit the tuner's report arrays)."""
+    import paper_2601_02826_amd as pq
+    src = open(os.path.join(ROOT, "include", "pqr.h")).read()
+    defs = dict(re.findall(r"#define (PQR_[A-Z_]+) (\d+)", src))
+    assert int(defs["PQR_TILE_VARIANTS"]) == pq.TILE_VARIANTS
+    assert int(defs["PQR_MLP_NOALLOC_MAX_ROWS"]) == pq.MLP_NOALLOC_MAX_ROWS
+    kh = open(os.path.join(ROOT, "paper_2601_02826_amd", "csrc", "pqr_kernels.h")).read()
+    m = re.search(r"kBgemmVariants = (\d+), kBaxpyVariants = (\d+)", kh)
+    assert (int(m.group(1)), int(m.group(2))) == (pq.BGEMM_VARIANTS, pq.BAXPY_VARIANTS)
+    assert max(pq.BGEMM_VARIANTS, pq.BAXPY_VARIANTS) <= pq.TILE_VARIANTS

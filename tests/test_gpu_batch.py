@@ -107,6 +107,7 @@ def test_every_launch_variant_gives_identical_iterates(K):
     product; each computes the same exact integer sums, so 300 iterations under every
     forced combination equal the default bit for bit, and the tuner's own choice (and
     the candidate times it measured) are reported."""
+    import paper_2601_02826_amd as pq
     n, p, G = 1500, 700, 3
     X, y = H.genotype_problem(n, p, seed=31)
     X1, _, _ = H.oracle_design(X, True)
@@ -114,7 +115,8 @@ def test_every_launch_variant_gives_identical_iterates(K):
     fr = np.resize(np.array([0.9, 0.6, 0.4, 0.3, 0.25, 0.2, 0.5, 0.7]), K)
     lams = np.array([f * pqr.lambda_max(X1, y, t) for f, t in zip(fr, taus)])
     ref = None
-    for o in range(1, 10):
+    for o in [1 + pq.TILE_VARIANTS * bv + av for bv in range(pq.BGEMM_VARIANTS)
+              for av in range(pq.BAXPY_VARIANTS)]:
         ctx = _ctx(X, G=G, tol_gap=1e-12, cert_every=100, max_iter=300, tile_override=o)
         res = ctx.solve_batch(y, taus, lams, allow_not_converged=True)
         B = np.stack([r["beta_std"] for r in res])
@@ -130,7 +132,8 @@ def test_every_launch_variant_gives_identical_iterates(K):
     t = ctx.batch_tiles(K)
     print(f"K={K}: tuner chose back-product {t['bgemm_variant']} {t['bgemm_ms']}, union product "
           f"{t['baxpy_variant']} {t['baxpy_ms']}")
-    assert 0 <= t["bgemm_variant"] < 3 and t["bgemm_ms"][t["bgemm_variant"]] == min(t["bgemm_ms"])
+    assert len(t["bgemm_ms"]) == pq.BGEMM_VARIANTS and len(t["baxpy_ms"]) == pq.BAXPY_VARIANTS
+    assert t["bgemm_ms"][t["bgemm_variant"]] == min(t["bgemm_ms"])
     # the union product is timed once its union holds 1024 columns (never at p = 700)
     assert t["baxpy_variant"] == -1 and t["union_cols"] == 0
     ctx.close()

@@ -51,7 +51,11 @@ def test_lla_stages(penalty, a, L):
 def test_lla_path_with_device_warm_start():
     """Along a lambda path, stage 0 of the next lambda may continue from the device state
     the previous lambda's last stage left (the paper's warm-started paths): the result
-    is certified and its weighted objective equals the zero-start solve's within tol."""
+    is certified, and its last stage solves the weighted problem of its own stage-0
+    answer.  The two stage-0 answers agree only to the certificate's tolerance, so the
+    last stages have slightly different weights w, w'; their optimal values then obey
+    |F(w) - F(w')| <= lambda sum_j |w_j - w'_j| max(|beta_j|, |beta'_j|) (F is the minimum
+    over beta of functions affine in w), which is asserted with the certificates' slack."""
     import paper_2601_02826_amd as pq
     n, p, tau, tol = 400, 150, 0.5, 1e-6
     X, y = H.genotype_problem(n, p, seed=73, n_causal=6)
@@ -64,7 +68,12 @@ def test_lla_path_with_device_warm_start():
     cold = ctx.solve_lla(y, tau, 0.25 * lmax, penalty="mcp", L=1)
     print(f"stage iterations: warm {warm['stage_iters']}, cold {cold['stage_iters']}")
     assert warm["rel_gap"] <= tol and cold["rel_gap"] <= tol
-    assert warm["primal"] == pytest.approx(cold["primal"], rel=3 * tol)
+    dw = np.abs(warm["weights"][1:] - cold["weights"][1:])
+    bmax = np.maximum(np.abs(warm["beta_std"][1:]), np.abs(cold["beta_std"][1:]))
+    bound = 0.25 * lmax * float(np.sum(dw * bmax)) + 3 * tol * cold["primal"]
+    print(f"primal warm {warm['primal']:.10f} cold {cold['primal']:.10f}, bound {bound:.3e}, "
+          f"max |dw| {dw.max():.3e}")
+    assert abs(warm["primal"] - cold["primal"]) <= bound
     assert warm["stage_iters"][0] < cold["stage_iters"][0]
     ctx.close()
 
