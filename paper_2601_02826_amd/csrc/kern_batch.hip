@@ -548,28 +548,31 @@ __global__ __launch_bounds__(256) void k_bbdigits(Geom g, BatchBufs b, int Kp) {
   }
 }
 
-// The product itself.  A wavefront owns 16 RT rows and every right-hand side;
-// per 64 union columns (one MFMA K step) it loads its rows of the 64 columns
-// (lane l: column l, 16 RT contiguous bytes), transposes them through LDS into
-// the B operand (lane: row l % 16, columns 16 (l / 16) .. +15), and issues
-// RT * NRT * 4 MFMAs with the coefficient digits as the A operand, so that the
-// result lands as (right-hand side, row) with rows contiguous.  The digits of a
-// step (NRT * 4 KB) are the same for every row: the WPB wavefronts of a block
-// stage them once per step in LDS (double-buffered, one barrier per step), so
-// the caches deliver them once per WPB * 16 RT rows instead of once per
-// wavefront.  Splits of the union along grid.y write FP64 partials.
-constexpr int kXStride = 68;   // LDS bytes per staged column (64 rows + 4, bank spread)
-constexpr int kXStrideTr = 72; // the same for 8-byte transposing reads (8-byte aligned)
-constexpr bool kBaxpyTr = true;  // transposing LDS reads (gfx950) for the B operand
-constexpr int kAxSets = 3;     // union product: X loaded this many 64-column steps ahead
+// The product itself.  A block of WPB wavefronts owns RB = 16 RT WPB consecutive
+// rows (inside one 1024-row chunk) and every right-hand side; wavefront wv owns rows
+// 16 RT wv .. +16 RT of them.  Per 64 union columns (one MFMA K step) the block loads
+// the RB rows of the 64 columns into one LDS tile (thread t: column t / WPB, 16-byte
+// pieces at 16 (t % WPB) + 16 WPB rt, so that the WPB threads of a column read 16 WPB
+// contiguous bytes per instruction: whole 128-byte lines at WPB >= 8), each wavefront
+// builds its B operand (lane: row l % 16, columns 16 (l / 16) .. +15) from the tile
+// with gfx950's transposing LDS reads, and issues RT * NRT * 4 MFMAs with the
+// coefficient digits as the A operand, so that the result lands as (right-hand side,
+// row) with rows contiguous.  The digits of a step (NRT * 4 KB, the same for every
+// row) are staged in LDS beside the tile.  Both are double-buffered (one barrier per
+// step).  Splits of the union along grid.y write exact int64 partials.
+constexpr int kAxSets = 3;     // union product: loads issued this many 64-column steps ahead
+constexpr int kXTilePad = 16;  // LDS bytes after each column of the X tile (bank spread
+                               // of the transposing reads; keeps 16-byte alignment)
 
-template <int RT, int NRT, int WPB, bool TR = kBaxpyTr>
+template <int RT, int NRT, int WPB>
 __global__ __launch_bounds__(64 * WPB) void k_baxpy(Geom g, BatchBufs b, int smax, int min_per) {
-  constexpr int kXS = TR ? kXStrideTr : kXStride;
+  constexpr int RB = 16 * RT * WPB;                     // rows of the block
+  constexpr int XSB = RB + kXTilePad;                   // LDS bytes per tile column
   constexpr int Kp = NRT * 16;
   constexpr int kDig = NRT * kCS * 64;                  // uint4 digit fragments per step
   constexpr int kDigPer = (kDig + 64 * WPB - 1) / (64 * WPB);
-  __shared__ __attribute__((aligned(16))) uint32_t xs[WPB][64 * kXS / 4];
+  static_assert(1024 % RB == 0, "a block's rows lie in one 1024-row chunk");
+  __shared__ __attribute__((aligned(16))) uint8_t xs[2][64 * XSB];
   __shared__ uint4 dg[2][kDig];                         // [buffer][(r * kCS + sl) * 64 + lane]
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -582,8 +585,9 @@ __global__ __launch_bounds__(64 * WPB) void k_baxpy(Geom g, BatchBufs b, int sma
                                                        // union still writes split 0)
   const int per = (nq + seff - 1) / seff;
   const int q0 = split * per, q1 = q0 + per < nq ? q0 + per : nq;
-  const int64_t rw = ((int64_t)blockIdx.x * WPB + wv) * (16 * RT);   // first row of the wave
-  const int64_t ch = rw >> 10, roff = rw & 1023;                     // 1024-row chunks
+  const int64_t rb = (int64_t)blockIdx.x * RB;          // first row of the block
+  const int64_t ch = rb >> 10, roff = rb & 1023;        // its 1024-row chunk
+  const int rw = wv * 16 * RT;                          // the wavefront's rows in the tile
   v4i acc[RT][NRT][kCS];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
@@ -591,21 +595,27 @@ __global__ __launch_bounds__(64 * WPB) void k_baxpy(Geom g, BatchBufs b, int sma
     for (int r = 0; r < NRT; ++r)
 #pragma unroll
       for (int sl = 0; sl < kCS; ++sl) acc[rt][r][sl] = v4i{0, 0, 0, 0};
-  uint32_t* xw = xs[wv];
   const int kb = lane >> 4, m = lane & 15;
+  const int xc = tid / WPB, xj = tid % WPB;             // this thread's tile column, piece
   const int nvg = (count + 15) / 16;                    // virtual groups with digits
-  // The column of union entry 64 qd + lane (past the count it re-reads the last
-  // entry; its digits are zero), and this thread's rows of a column.  Entries are
-  // loaded two steps before the rows they address: the wait for an entry then
-  // covers only loads issued before it, never the X loads still in flight.
+  // The column of union entry 64 qd + xc (past the count it re-reads the last entry;
+  // its digits are zero), and this thread's pieces of a column.
   auto fetch_j = [&](int qd) -> int {
-    const int il = 64 * qd + lane < count ? 64 * qd + lane : count - 1;
+    const int il = 64 * qd + xc < count ? 64 * qd + xc : count - 1;
     return b.list[il];
   };
   auto fetch_x = [&](int64_t jl, uint4 (&xv)[RT]) {
-    const uint8_t* src = g.seg(jl, ch) + roff;
+    const uint8_t* src = g.seg(jl, ch) + roff + 16 * xj;
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt) xv[rt] = *reinterpret_cast<const uint4*>(src + 16 * rt);
+    for (int rt = 0; rt < RT; ++rt)
+      xv[rt] = *reinterpret_cast<const uint4*>(src + 16 * WPB * rt);
+  };
+  auto store_x = [&](int buf, const uint4 (&xv)[RT]) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      uint32_t* d = reinterpret_cast<uint32_t*>(&xs[buf][xc * XSB + 16 * xj + 16 * WPB * rt]);
+      d[0] = xv[rt].x; d[1] = xv[rt].y; d[2] = xv[rt].z; d[3] = xv[rt].w;
+    }
   };
   // This thread's share of the step's digits: fragment f = (r * kCS + sl) * 64 + l
   // holds the A operand of MFMA lane l: digits of (rhs r*16 + l % 16, virtual group
@@ -633,98 +643,82 @@ __global__ __launch_bounds__(64 * WPB) void k_baxpy(Geom g, BatchBufs b, int sma
     }
   };
   // NS register sets in rotation, the step's set a compile-time index (the loop body
-  // is NS steps): at step qd set c = (qd - q0) % NS holds X of step qd, which is
-  // staged, and is then refilled with X and digits of step qd + NS, so that X loads
-  // run NS steps ahead of their MFMAs with no register moves (a move would wait for
-  // its load).  The column index of step qd + NS was loaded at step qd - NS.  Per
-  // step the digit loads come first and the index load last, so that the waits
-  // (store of step qd + 1's digits, index of step qd + NS) never cover a later X load.
-  // Every step of the body runs, also past q1 (on the last step's columns with zero
-  // digits): a skipped step would leave the compiler's wait counts at zero.
+  // is NS steps): at step qd set c = (qd - q0) % NS is free (its step's tile and digits
+  // were stored at step qd - 1) and is refilled with step qd + NS, while set (c + 1) %
+  // NS is stored into the other LDS buffers for step qd + 1, so that loads run NS - 1
+  // steps ahead of their stores with no register moves (a move would wait for its
+  // load).  The column index of step qd + NS was loaded at step qd - NS.  Per step the
+  // digit loads come first and the index load last, so that the waits (stores of step
+  // qd + 1, index of step qd + NS) never cover a later X load.  Every step of the body
+  // runs, also past q1 (on the last step's columns with zero digits): a skipped step
+  // would leave the compiler's wait counts at zero.
   constexpr int NS = kAxSets;
   uint4 xset[NS][RT];
   uint4 dset[NS][kDigPer];
   int jset[NS];
   auto clampq = [&](int q) { return q < q1 ? q : q1 - 1; };
   if (q0 < q1) {
-    // (the index loads first: the loop's wait counts hold from its first step on)
-    static_for<NS>([&](auto I) { jset[I.value] = fetch_j(clampq(q0 + NS + I.value)); });
+    // the first NS steps' indices, then per step the loop's own order (digits, X,
+    // index of the step NS later), so that the wait counts the compiler derives at
+    // the loop's entry are those of its steady state
+    int j0[NS];
+    static_for<NS>([&](auto I) { j0[I.value] = fetch_j(clampq(q0 + I.value)); });
     static_for<NS>([&](auto I) {
-      const int q = clampq(q0 + I.value);
-      fetch_d(q, dset[I.value]);
-      fetch_x(fetch_j(q), xset[I.value]);
+      fetch_d(clampq(q0 + I.value), dset[I.value]);
+      fetch_x(j0[I.value], xset[I.value]);
+      jset[I.value] = fetch_j(clampq(q0 + NS + I.value));
     });
     store_d(q0 & 1, dset[0], q0);
+    store_x(q0 & 1, xset[0]);
   }
   __syncthreads();
   for (int qb = q0; qb < q1; qb += NS) {
-    static_for<NS>([&](auto I) {
-      constexpr int c = I.value;
+    static_for<NS>([&](auto I) __attribute__((always_inline)) {   // inlined: the register
+      constexpr int c = I.value;                                   // sets must not escape
       const int qd = qb + c;
-      {
-        // stage: column `lane` at xw[lane * kXS / 4 ...], rows 0 .. 16 RT - 1
+      const uint8_t* xb = xs[qd & 1] + rw;
+      const uint4* dgb = dg[qd & 1];
+      v4i bf[RT];
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-          uint32_t* d = xw + lane * (kXS / 4) + 4 * rt;
-          d[0] = xset[c][rt].x; d[1] = xset[c][rt].y; d[2] = xset[c][rt].z; d[3] = xset[c][rt].w;
-        }
-        __builtin_amdgcn_wave_barrier();
-        const uint8_t* xb = reinterpret_cast<const uint8_t*>(xw);
-        const uint4* dgb = dg[qd & 1];
-        v4i bf[RT];
+      for (int rt = 0; rt < RT; ++rt) {
+        // B operand: row rw + 16 rt + m, columns 16 kb + 0..15.  Transposing 8-byte
+        // reads (ds_read_b64_tr_b8): in each group of 16 lanes, byte b of the result
+        // of lane 16 g + 8 e + j is byte j of what lane 16 g + 2 b + e read.  Lane L
+        // reads rows 8 (L & 1) .. +7 of column 16 (L >> 4) + 8 h + ((L >> 1) & 7),
+        // so lane (m, kb) receives row m of columns 16 kb + 8 h .. +7 in order.
+        v2i r[2];
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-          // B operand: row 16 rt + m, columns 16 kb + 0..15
-          if constexpr (TR) {
-            // transposing 8-byte reads (ds_read_b64_tr_b8): in each group of 16
-            // lanes, byte b of the result of lane 16 g + 8 e + j is byte j of what
-            // lane 16 g + 2 b + e read.  Lane L reads rows 8 (L & 1) .. +7 of column
-            // 16 (L >> 4) + 8 h + ((L >> 1) & 7), so lane (m, kb) receives row m of
-            // columns 16 kb + 8 h .. +7 in order.
-            v2i r[2];
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-              r[h] = __builtin_amdgcn_ds_read_tr8_b64_v2i32(
-                  (__attribute__((address_space(3))) v2i*)(xb +
-                      (16 * kb + 8 * h + ((lane >> 1) & 7)) * kXS + 8 * (lane & 1) + 16 * rt));
-            bf[rt] = v4i{r[0].x, r[0].y, r[1].x, r[1].y};
-          } else {
-            uint32_t w[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const uint8_t* p = xb + (16 * kb + 4 * q) * kXS + 16 * rt + m;
-              w[q] = (uint32_t)p[0] | ((uint32_t)p[kXS] << 8) | ((uint32_t)p[2 * kXS] << 16) |
-                     ((uint32_t)p[3 * kXS] << 24);
-            }
-            bf[rt] = v4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
-          }
-        }
-#pragma unroll
-        for (int r = 0; r < NRT; ++r)
-#pragma unroll
-          for (int sl = 0; sl < kCS; ++sl) {
-            const uint4 a4 = dgb[(r * kCS + sl) * 64 + lane];
-            const v4i af = v4i{(int)a4.x, (int)a4.y, (int)a4.z, (int)a4.w};
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
-              acc[rt][r][sl] =
-                  __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf[rt], acc[rt][r][sl], 0, 0, 0);
-          }
-        __builtin_amdgcn_wave_barrier();
-        // every wavefront has finished reading buffer (qd + 1) & 1 (step qd - 1)
-        // before the barrier that ended that step, so it can be refilled now
-        store_d((qd + 1) & 1, dset[(c + 1) % NS], qd + 1);
-        __builtin_amdgcn_sched_barrier(0);
-        const int jx = jset[c];
-        fetch_d(clampq(qd + NS), dset[c]);
-        fetch_x(jx, xset[c]);
-        jset[c] = fetch_j(clampq(qd + 2 * NS));
-        __builtin_amdgcn_sched_barrier(0);
-        __syncthreads();
+        for (int h = 0; h < 2; ++h)
+          r[h] = __builtin_amdgcn_ds_read_tr8_b64_v2i32(
+              (__attribute__((address_space(3))) v2i*)(xb +
+                  (16 * kb + 8 * h + ((lane >> 1) & 7)) * XSB + 8 * (lane & 1) + 16 * rt));
+        bf[rt] = v4i{r[0].x, r[0].y, r[1].x, r[1].y};
       }
+#pragma unroll
+      for (int r = 0; r < NRT; ++r)
+#pragma unroll
+        for (int sl = 0; sl < kCS; ++sl) {
+          const uint4 a4 = dgb[(r * kCS + sl) * 64 + lane];
+          const v4i af = v4i{(int)a4.x, (int)a4.y, (int)a4.z, (int)a4.w};
+#pragma unroll
+          for (int rt = 0; rt < RT; ++rt)
+            acc[rt][r][sl] =
+                __builtin_amdgcn_mfma_i32_16x16x64_i8(af, bf[rt], acc[rt][r][sl], 0, 0, 0);
+        }
+      // every wavefront has finished reading buffers (qd + 1) & 1 (step qd - 1)
+      // before the barrier that ended that step, so they can be refilled now
+      store_d((qd + 1) & 1, dset[(c + 1) % NS], qd + 1);
+      store_x((qd + 1) & 1, xset[(c + 1) % NS]);
+      __builtin_amdgcn_sched_barrier(0);
+      const int jx = jset[c];
+      fetch_d(clampq(qd + NS), dset[c]);
+      fetch_x(jx, xset[c]);
+      jset[c] = fetch_j(clampq(qd + 2 * NS));
+      __builtin_amdgcn_sched_barrier(0);
+      __syncthreads();
     });
   }
-  // lane holds C[rhs = r*16 + 4 kb + i][row = rw + 16 rt + m]
+  // lane holds C[rhs = r*16 + 4 kb + i][row = rb + rw + 16 rt + m]
 #pragma unroll
   for (int r = 0; r < NRT; ++r)
 #pragma unroll
@@ -735,7 +729,7 @@ __global__ __launch_bounds__(64 * WPB) void k_baxpy(Geom g, BatchBufs b, int sma
         long long P = 0;
 #pragma unroll
         for (int sl = 0; sl < kCS; ++sl) P = P * 128 + (long long)acc[rt][r][sl][i];
-        b.partial[((int64_t)split * Kp + k) * g.n_pad + rw + 16 * rt + m] = P;
+        b.partial[((int64_t)split * Kp + k) * g.n_pad + rb + rw + 16 * rt + m] = P;
       }
     }
 }
@@ -992,7 +986,8 @@ hipError_t launch_bgemm_variant(const Geom& g, const BatchBufs& b, int Kp, int v
 
 // Union product: rows per wavefront 16 RT with RT * NRT * 16 <= 128 accumulator
 // registers; variants 0, 1, 2 = blocks of 8, 4 and 16 wavefronts sharing the staged
-// digits (n_pad is a multiple of 1024 >= 16 W RT rows); splits of the union along y.
+// tile and digits (n_pad is a multiple of 1024 >= 16 W RT rows); splits of the union
+// along y.
 // The split count (the results do not depend on it: exact integer split sums) is
 // the largest that lets every block of the grid be resident at once, so that a
 // large union runs as one round of blocks instead of ending in a partly empty
