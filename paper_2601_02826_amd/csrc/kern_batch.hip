@@ -67,12 +67,14 @@ __global__ __launch_bounds__(256) void k_bdigits(BatchBufs b, int64_t n, int64_t
     b.tpart[(int64_t)blockIdx.x * Kp + k] = red[0] + red[1] + red[2] + red[3];
 }
 
-__global__ void k_bdsum(BatchBufs b, int nblk, int Kp) {
-  const int k = threadIdx.x;
-  if (k >= Kp) return;
+// one wavefront per right-hand side k (grid Kp): exact integer sums, any order
+__global__ __launch_bounds__(64) void k_bdsum(BatchBufs b, int nblk, int Kp) {
+  const int k = blockIdx.x, lane = threadIdx.x;
   long long s = 0;
-  for (int q = 0; q < nblk; ++q) s += b.tpart[(int64_t)q * Kp + k];
-  b.tsumq[k] = s;
+  for (int q = lane; q < nblk; q += 64) s += b.tpart[(int64_t)q * Kp + k];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) b.tsumq[k] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -788,14 +790,21 @@ __global__ __launch_bounds__(256) void k_bupdate(BatchBufs b, int64_t n, int64_t
   }
 }
 
-__global__ void k_bfinal(BatchBufs b, int nblk, int Kp) {
-  const int k = threadIdx.x;
-  if (k >= Kp) return;
+// one wavefront per right-hand side k (grid Kp): each lane sums the blocks q = lane,
+// lane + 64, ... in order, then a fixed butterfly combines the lanes (deterministic)
+__global__ __launch_bounds__(64) void k_bfinal(BatchBufs b, int nblk, int Kp) {
+  const int k = blockIdx.x, lane = threadIdx.x;
   double s0 = 0, mx = 0, s2 = 0, s3 = 0, s4 = 0;
-  for (int q = 0; q < nblk; ++q) {
+  for (int q = lane; q < nblk; q += 64) {
     const double* o = b.bpart + ((int64_t)q * Kp + k) * 8;
     s0 += o[0]; mx = fmax(mx, o[1]); s2 += o[2]; s3 += o[3]; s4 += o[4];
   }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    s0 += __shfl_xor(s0, off); mx = fmax(mx, __shfl_xor(mx, off));
+    s2 += __shfl_xor(s2, off); s3 += __shfl_xor(s3, off); s4 += __shfl_xor(s4, off);
+  }
+  if (lane != 0) return;
   b.tsum[k] = s0;
   // digit scale: the smallest power of two >= max |theta_k| (1 while theta_k = 0)
   int ex = 0;
@@ -1078,7 +1087,7 @@ hipError_t launch_batch_iteration(const Geom& g, const BatchBufs& b, int Kp, dou
   const unsigned nb = (unsigned)(g.n_pad / 256);
   const int nrt = Kp / 16;
   hipLaunchKernelGGL(k_bdigits, dim3(nb, Kp), dim3(256), 0, s, b, g.n, g.n_pad, Kp);
-  hipLaunchKernelGGL(k_bdsum, dim3(1), dim3(128), 0, s, b, (int)nb, Kp);
+  hipLaunchKernelGGL(k_bdsum, dim3(Kp), dim3(64), 0, s, b, (int)nb, Kp);
   hipError_t e = launch_bgemm_variant(g, b, Kp, tiles.bgemm, s, ev0, ev1);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_bcount, dim3(kCompactBlocks), dim3(1024), 0, s, g.ngroups(), b, nrt);
@@ -1091,7 +1100,7 @@ hipError_t launch_batch_iteration(const Geom& g, const BatchBufs& b, int Kp, dou
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_bupdate, dim3(nb, Kp), dim3(256), 0, s, b, g.n, g.n_pad, Kp, mu, sigma,
                      smax, min_per);
-  hipLaunchKernelGGL(k_bfinal, dim3(1), dim3(128), 0, s, b, (int)nb, Kp);
+  hipLaunchKernelGGL(k_bfinal, dim3(Kp), dim3(64), 0, s, b, (int)nb, Kp);
   return hipGetLastError();
 }
 
