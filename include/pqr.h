@@ -102,7 +102,7 @@ typedef struct {
                            With opt.profile the kernels are always launched directly. */
   int tile_override;    /* 0 (default) = batched solves choose their launch variants by
                            timing them (pqr_batch_tiles); 1 + PQR_TILE_VARIANTS b + a
-                           forces back-product variant b (0..2) and union-product
+                           forces back-product variant b (0..3) and union-product
                            variant a (0..2), for tests */
 } pqr_options;
 
@@ -258,7 +258,7 @@ pqr_status pqr_solve_batch(pqr_ctx* ctx, const double* y, int K, const double* t
                            const double* lambdas, const double* weights, pqr_result* outs);
 
 /* The launch variants the autotuner chose for batched solves of width K on this
- * context, and the mean time (ms) it measured for each candidate: the three of the
+ * context, and the mean time (ms) it measured for each candidate: the four of the
  * back-product (bgemm_ms, host, PQR_TILE_VARIANTS doubles, unused entries 0; timed on
  * the first batched solve of that width before its iterations) and the three of the
  * union product (baxpy_ms, same size; timed at the end of the first chunk of

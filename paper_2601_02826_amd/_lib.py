@@ -18,7 +18,7 @@ FMT = {"f64": 0, "f32": 1, "bf16": 2, "fp8": 3, "i8": 4, "2bit": 5}
 ITER = {"f32": 0, "f64": 1}
 START = {"zero": 0, "host": 1, "device": 2}
 TILE_VARIANTS = 8                      # PQR_TILE_VARIANTS: size of the tuner's time arrays
-BGEMM_VARIANTS, BAXPY_VARIANTS = 3, 3  # launch variants of the back- and union products
+BGEMM_VARIANTS, BAXPY_VARIANTS = 4, 3  # launch variants of the back- and union products
 
 _c_dp = ctypes.POINTER(ctypes.c_double)
 

@@ -960,7 +960,10 @@ hipError_t launch_cert_pass(const Geom& g, const CertArgs& c, int Kc, hipStream_
 // block fills a CU and a staged digit tile serves 8 GW / wps groups; with 3 to 8
 // tiles the set's A fragments are staged once in LDS too), variant 1 the same with
 // GW = 2 (half the accumulators, twice the blocks), variant 2 for 1 or 2 tiles a
-// longer digit tile (SPT 4, one barrier per 256 rows) or the shared-A form.
+// longer digit tile (SPT 4, one barrier per 256 rows) or the shared-A form; variant
+// 3 for 1 or 2 tiles takes 3 groups per wavefront in blocks of 12 wavefronts (about
+// 150 VGPRs, three wavefronts per SIMD: a 1M-column design is 6.8 rounds of blocks on
+// 256 CUs instead of 7.6, and a CU holds 12 wavefronts instead of 8).
 // DL = ceil(12 SPT Kp / (64 WPB)) digit loads per thread and tile.
 
 hipError_t launch_bgemm_variant(const Geom& g, const BatchBufs& b, int Kp, int v, hipStream_t s,
@@ -968,6 +971,11 @@ hipError_t launch_bgemm_variant(const Geom& g, const BatchBufs& b, int Kp, int v
   const CertArgs c{};
   const int nrt = Kp / 16;
   if (v < 0 || v >= bgemm_variants()) return hipErrorInvalidValue;
+  if (v == 3) {   // 12-wavefront blocks, 3 groups per wavefront (1 or 2 tiles; else variant 0)
+    if (nrt == 1) return launch_bgemm<1, 3, 1, 2, 12, 2, kBS, false>(g, b, c, Kp, 1, s, ev0, ev1);
+    if (nrt == 2) return launch_bgemm<2, 3, 1, 2, 12, 2, kBS, false>(g, b, c, Kp, 1, s, ev0, ev1);
+    v = 0;
+  }
   switch (nrt) {
     case 1:
       if (v == 0) return launch_bgemm<1, 4, 1, 2, 8, 2, kBS, false>(g, b, c, Kp, 1, s, ev0, ev1);

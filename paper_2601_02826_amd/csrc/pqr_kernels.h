@@ -222,7 +222,7 @@ struct BatchBufs {
 struct BatchTiles {
   int bgemm = 0, baxpy = 0;
 };
-constexpr int kBgemmVariants = 3, kBaxpyVariants = 3;
+constexpr int kBgemmVariants = 4, kBaxpyVariants = 3;
 constexpr int kBaxpySplits = 16;   // most splits of the union product (partial buffer)
 inline int bgemm_variants() { return kBgemmVariants; }
 inline int baxpy_variants() { return kBaxpyVariants; }
