@@ -503,15 +503,24 @@ __global__ __launch_bounds__(256) void k_bbmax(Geom g, BatchBufs b, int Kp) {
 // the per-block sums of m_j U_kj; d_k from the maxima of k_bbmax.
 __global__ __launch_bounds__(256) void k_bbdigits(Geom g, BatchBufs b, int Kp) {
   __shared__ double dk[128];
+  __shared__ double pm[256];
   const int t = threadIdx.x, c = t & 15, nrt = Kp / 16;
-  if (t < Kp) {
+  {
+    // d_k from the kDigitBlocks partial maxima: 256 / Kp threads per k, then one per k
+    const int per = 256 / Kp, kk = t % Kp, part = t / Kp;
     double mx = 0;
-    for (int q = 0; q < kDigitBlocks; ++q) mx = fmax(mx, b.pmax[(int64_t)q * Kp + t]);
-    int ex = 0;
-    const double fr = frexp(mx > 0 ? mx : 1.0, &ex);
-    const double d = ldexp(1.0, fr == 0.5 ? ex - 1 : ex);   // smallest power of two >= mx
-    dk[t] = d;
-    if (blockIdx.x == 0) b.bscale[t] = d;
+    if (part < per)
+      for (int q = part; q < kDigitBlocks; q += per) mx = fmax(mx, b.pmax[(int64_t)q * Kp + kk]);
+    pm[t] = mx;
+    __syncthreads();
+    if (t < Kp) {
+      for (int u = 1; u < per; ++u) mx = fmax(mx, pm[u * Kp + t]);
+      int ex = 0;
+      const double fr = frexp(mx > 0 ? mx : 1.0, &ex);
+      const double d = ldexp(1.0, fr == 0.5 ? ex - 1 : ex);   // smallest power of two >= mx
+      dk[t] = d;
+      if (blockIdx.x == 0) b.bscale[t] = d;
+    }
   }
   __syncthreads();
   const int count = *b.count;
@@ -746,14 +755,15 @@ __global__ __launch_bounds__(256) void k_bupdate(BatchBufs b, int64_t n, int64_t
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int seff = bsplits((*b.count + 63) / 64, smax, min_per);
   double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  // mean correction of X~ B: d_k 2^-27 sum_j m_j U_kj (fixed block order)
-  __shared__ double offk;
-  if (threadIdx.x == 0) {
-    double o = 0;
-    for (int q = 0; q < kDigitBlocks; ++q) o += b.poff[(int64_t)q * Kp + k];
-    offk = o * (b.bscale[k] / (double)(1ll << kCBits));
+  // mean correction of X~ B: d_k 2^-27 sum_j m_j U_kj over the kDigitBlocks (= 256,
+  // one per thread) partials, summed by the block's fixed reduction tree
+  static_assert(kDigitBlocks == 256, "one digit-block partial per thread");
+  double offk;
+  {
+    double o[1] = {b.poff[(int64_t)threadIdx.x * Kp + k]};
+    block_sum<256, 1, double>(o, red);
+    offk = o[0] * (b.bscale[k] / (double)(1ll << kCBits));
   }
-  __syncthreads();
   if (i < n && k < b.K && b.kact[k]) {
     long long P = 0;   // exact: the splits' integer sums
     for (int sp = 0; sp < seff; ++sp) P += b.partial[((int64_t)sp * Kp + k) * n_pad + i];
