@@ -207,6 +207,67 @@ __global__ __launch_bounds__(1024) void k_scatter(int64_t ngroups, IterBufs<T> b
   scatter_body<T>(ngroups, b, eta0, step_intercept, blockIdx.x);
 }
 
+// The same compaction in one block for designs of at most kCompactOneBlock groups,
+// where two launches of kCompactBlocks blocks cost more than the work: the list (groups
+// in order), the count, the intercept step and the norms (summed here by one block's
+// tree, so the norms of the monitor can differ in their last bits from the two-kernel
+// form; the list, the count and the intercept are identical).
+constexpr int64_t kCompactOneBlock = 8192;
+template <typename T>
+__global__ __launch_bounds__(1024) void k_compact1(int64_t ngroups, IterBufs<T> b, double eta0,
+                                                   int step_intercept) {
+  __shared__ int wcnt[16];
+  __shared__ double red[4 * 16];
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  double s[4] = {0, 0, 0, 0};
+  int base = 0;
+  for (int64_t tile = 0; tile < ngroups; tile += 1024) {
+    const int64_t gi = tile + t;
+    const bool in = gi < ngroups;
+    const bool f = in && b.gflag[gi] != 0;
+    if (in)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s[k] += (double)b.gnorm[gi * 4 + k];
+    const unsigned long long bal = __ballot(f);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wcnt[wid] = __popcll(bal);
+    __syncthreads();
+    int woff = 0, tot = 0;
+    for (int w = 0; w < 16; ++w) {
+      woff += w < wid ? wcnt[w] : 0;
+      tot += wcnt[w];
+    }
+    if (f) b.list[base + woff + before] = (int)gi;
+    base += tot;
+    __syncthreads();
+  }
+  block_sum<1024, 4, double>(s, red);
+  if (t == 0) {
+    Ctl* c = b.ctl;
+    double b0 = c->beta0, b0n = b0;
+    if (step_intercept) b0n = b0 + c->sum_theta / eta0;   // intercept: lambda_0 = 0
+    const double d0 = b0n - b0;
+    c->beta0 = b0n;
+    c->nb[0] = s[0] + d0 * d0;
+    c->nb[1] = s[1] + b0n * b0n;
+    c->nb[2] = s[2] + eta0 * d0 * d0;
+    c->nb[3] = s[3];
+    c->count = base;
+  }
+}
+
+template <typename T>
+static void launch_compaction(int64_t ng, const IterBufs<T>& b, double eta0, int step_intercept,
+                              hipStream_t s) {
+  if (ng <= kCompactOneBlock) {
+    hipLaunchKernelGGL((k_compact1<T>), dim3(1), dim3(1024), 0, s, ng, b, eta0, step_intercept);
+    return;
+  }
+  hipLaunchKernelGGL((k_count<T>), dim3(kCompactBlocks), dim3(1024), 0, s, ng, b);
+  hipLaunchKernelGGL((k_scatter<T>), dim3(kCompactBlocks), dim3(1024), 0, s, ng, b, eta0,
+                     step_intercept);
+}
+
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int splits_in_use(int count, int smax, int min_per) {
   const int s = (count + min_per - 1) / min_per;
@@ -229,17 +290,37 @@ __device__ __forceinline__ void axpy_body(const Geom& g, const IterBufs<T>& b, i
 #pragma unroll
   for (int r = 0; r < RPL; ++r) acc[r] = 0;
   double off = 0;
+  // The group's 16 coefficients first, then the rows of its nonzero columns loaded
+  // CB columns at a time before any is used (their loads overlap), then the products
+  // in column order (the same arithmetic as one column at a time).
+  constexpr int kRawRegs = (int)(sizeof(Raw<FMT, RPL>) / 4);
+  constexpr int CB = kRawRegs <= 4 ? 16 : (kRawRegs <= 8 ? 8 : (kRawRegs <= 16 ? 4 : 2));
   for (int e = e0; e < e1; ++e) {
     const int64_t grp = b.list[e];
+    double bj[kGroup];
+    uint32_t nzm = 0;   // wave-uniform: bit c = column c has a nonzero coefficient
+#pragma unroll
     for (int c = 0; c < kGroup; ++c) {
       const int64_t j = grp * kGroup + c;
-      const double bj = (double)b.beta[j] * (double)b.cinv[j];   // coefficient on the raw column
-      if (bj != 0.0) {
-        double x[RPL];
-        load_rows<FMT, RPL, double>(g.seg(j, ch), (int64_t)lane * RPL, x);
+      bj[c] = (double)b.beta[j] * (double)b.cinv[j];   // coefficient on the raw column
+      nzm |= (bj[c] != 0.0 ? 1u : 0u) << c;
+    }
 #pragma unroll
-        for (int r = 0; r < RPL; ++r) acc[r] = fma(x[r], bj, acc[r]);
-        off = fma((double)b.cm[j], bj, off);
+    for (int cb = 0; cb < kGroup; cb += CB) {
+      if (((nzm >> cb) & ((1u << CB) - 1u)) == 0u) continue;
+      Raw<FMT, RPL> raw[CB];
+#pragma unroll
+      for (int c = 0; c < CB; ++c)
+        if ((nzm >> (cb + c)) & 1u)
+          raw[c] = load_raw<FMT, RPL>(g.seg(grp * kGroup + cb + c, ch), (int64_t)lane * RPL);
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        if (!((nzm >> (cb + c)) & 1u)) continue;
+        double x[RPL];
+        decode<FMT, RPL, double>(raw[c], x);
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) acc[r] = fma(x[r], bj[cb + c], acc[r]);
+        off = fma((double)b.cm[grp * kGroup + cb + c], bj[cb + c], off);
       }
     }
   }
@@ -429,8 +510,7 @@ static void launch_fmt(const Geom& g, const IterBufs<T>& b, const IterParams& ip
   if (ev0) (void)hipEventRecord(ev0, s);
   hipLaunchKernelGGL((k_sweep<FMT, RPL, T>), dim3((unsigned)((ng + 3) / 4)), dim3(256), 0, s, g, b);
   if (ev1) (void)hipEventRecord(ev1, s);
-  hipLaunchKernelGGL((k_count<T>), dim3(kCompactBlocks), dim3(1024), 0, s, ng, b);
-  hipLaunchKernelGGL((k_scatter<T>), dim3(kCompactBlocks), dim3(1024), 0, s, ng, b, ip.eta0, 1);
+  launch_compaction<T>(ng, b, ip.eta0, 1, s);
   hipLaunchKernelGGL((k_axpy<FMT, RPL, T>), dim3((unsigned)((g.nchunks() + 3) / 4), ip.smax),
                      dim3(256), 0, s, g, b, ip.smax, ip.min_per);
   hipLaunchKernelGGL((k_update<T>), dim3((unsigned)(g.n_pad / 256)), dim3(256), 0, s, b, ip, g.n,
@@ -453,8 +533,7 @@ template <int FMT, int RPL, typename T>
 static void prepare_fmt(const Geom& g, const IterBufs<T>& b, const IterParams& ip, hipStream_t s) {
   const int64_t ng = g.ngroups();
   hipLaunchKernelGGL((k_flags<T>), dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, s, ng, b);
-  hipLaunchKernelGGL((k_count<T>), dim3(kCompactBlocks), dim3(1024), 0, s, ng, b);
-  hipLaunchKernelGGL((k_scatter<T>), dim3(kCompactBlocks), dim3(1024), 0, s, ng, b, ip.eta0, 0);
+  launch_compaction<T>(ng, b, ip.eta0, 0, s);
   hipLaunchKernelGGL((k_axpy<FMT, RPL, T>), dim3((unsigned)((g.nchunks() + 3) / 4), ip.smax),
                      dim3(256), 0, s, g, b, ip.smax, ip.min_per);
   hipLaunchKernelGGL((k_init_r<T>), dim3((unsigned)(g.n_pad / 256)), dim3(256), 0, s, b, ip, g.n,
@@ -513,8 +592,7 @@ template <typename T>
 hipError_t launch_active_list(const Geom& g, const IterBufs<T>& b, hipStream_t s) {
   const int64_t ng = g.ngroups();
   hipLaunchKernelGGL((k_flags<T>), dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, s, ng, b);
-  hipLaunchKernelGGL((k_count<T>), dim3(kCompactBlocks), dim3(1024), 0, s, ng, b);
-  hipLaunchKernelGGL((k_scatter<T>), dim3(kCompactBlocks), dim3(1024), 0, s, ng, b, 1.0, 0);
+  launch_compaction<T>(ng, b, 1.0, 0, s);
   return hipGetLastError();
 }
 template hipError_t launch_active_list<float>(const Geom&, const IterBufs<float>&, hipStream_t);
