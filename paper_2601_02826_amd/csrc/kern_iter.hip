@@ -290,29 +290,35 @@ __device__ __forceinline__ void axpy_body(const Geom& g, const IterBufs<T>& b, i
 #pragma unroll
   for (int r = 0; r < RPL; ++r) acc[r] = 0;
   double off = 0;
-  // The group's 16 coefficients first, then the rows of its nonzero columns loaded
-  // CB columns at a time before any is used (their loads overlap), then the products
-  // in column order (the same arithmetic as one column at a time).
+  // The group's 16 coefficients first, then the rows of CB columns loaded with no
+  // branch between the loads (so that they are in flight together; a column whose
+  // coefficient is zero re-reads the rows of the group's first nonzero column, a cache
+  // hit, and is skipped below), then the products of the nonzero columns in column
+  // order (the same arithmetic as one column at a time).
   constexpr int kRawRegs = (int)(sizeof(Raw<FMT, RPL>) / 4);
   constexpr int CB = kRawRegs <= 4 ? 16 : (kRawRegs <= 8 ? 8 : (kRawRegs <= 16 ? 4 : 2));
   for (int e = e0; e < e1; ++e) {
     const int64_t grp = b.list[e];
-    double bj[kGroup];
+    double bj[kGroup], cmj[kGroup];
     uint32_t nzm = 0;   // wave-uniform: bit c = column c has a nonzero coefficient
 #pragma unroll
     for (int c = 0; c < kGroup; ++c) {
       const int64_t j = grp * kGroup + c;
       bj[c] = (double)b.beta[j] * (double)b.cinv[j];   // coefficient on the raw column
+      cmj[c] = (double)b.cm[j];
       nzm |= (bj[c] != 0.0 ? 1u : 0u) << c;
     }
+    if (nzm == 0u) continue;
+    const int cfirst = __ffs((int)nzm) - 1;
 #pragma unroll
     for (int cb = 0; cb < kGroup; cb += CB) {
       if (((nzm >> cb) & ((1u << CB) - 1u)) == 0u) continue;
       Raw<FMT, RPL> raw[CB];
 #pragma unroll
-      for (int c = 0; c < CB; ++c)
-        if ((nzm >> (cb + c)) & 1u)
-          raw[c] = load_raw<FMT, RPL>(g.seg(grp * kGroup + cb + c, ch), (int64_t)lane * RPL);
+      for (int c = 0; c < CB; ++c) {
+        const int cc = ((nzm >> (cb + c)) & 1u) ? cb + c : cfirst;
+        raw[c] = load_raw<FMT, RPL>(g.seg(grp * kGroup + cc, ch), (int64_t)lane * RPL);
+      }
 #pragma unroll
       for (int c = 0; c < CB; ++c) {
         if (!((nzm >> (cb + c)) & 1u)) continue;
@@ -320,7 +326,7 @@ __device__ __forceinline__ void axpy_body(const Geom& g, const IterBufs<T>& b, i
         decode<FMT, RPL, double>(raw[c], x);
 #pragma unroll
         for (int r = 0; r < RPL; ++r) acc[r] = fma(x[r], bj[cb + c], acc[r]);
-        off = fma((double)b.cm[grp * kGroup + cb + c], bj[cb + c], off);
+        off = fma(cmj[cb + c], bj[cb + c], off);
       }
     }
   }
