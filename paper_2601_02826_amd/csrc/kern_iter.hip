@@ -5,7 +5,8 @@
 //              weighted soft threshold of eq. beta_update.
 //   k_count, k_scatter  the ordered list of column groups holding a nonzero
 //              coefficient, the sweep's norm partials, and the intercept
-//              (lambda_0 = 0, so its update is a plain step).
+//              (lambda_0 = 0, so its update is a plain step); k_compact1 does
+//              the same in one block for designs of at most 8192 groups.
 //   k_axpy     s = X~ beta^{k+1} over the nonzero coefficients only: the
 //              partial products X_g beta_g of the paper, gathered by column
 //              and reduced in a fixed order (no atomics).
