@@ -221,7 +221,7 @@ def test_error_paths():
 
 
 def test_h_norm_monitor_reports_divergence():
-    """eta forced to 0.1% of mu*Lambda: the successive differences grow, the driver
+    """eta forced to 0.1% of mu*Lambda: the successive differences grow, the solver
     doubles eta twice and then reports PQR_ERR_DIVERGED (host-forced condition; every
     kernel still exits normally)."""
     import paper_2601_02826_amd as pq
